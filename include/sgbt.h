@@ -1,0 +1,186 @@
+/*
+ * sgbt -- stochastic Galerkin solves with block-triangular preconditioning on AMD MI355X (gfx950).
+ *
+ * C ABI of libsgbt.so.  The library solves the stochastic Galerkin system of
+ * Zheng, Lin and Xu, "Block triangular preconditioning for stochastic Galerkin
+ * method" (arXiv:1304.1755):
+ *
+ *     A U = F,   A = G_0 (x) K_0 + sum_{k=1..m} G_k (x) K_k          (Sec. 3.1, eq. (tensor-product))
+ *
+ * for -div(a grad u) = 1 on the unit square with zero Dirichlet data, Q1
+ * elements on a uniform n x n grid, a truncated Karhunen-Loeve coefficient
+ * a = a0 + sigma sum_k s_k b_k(x) xi_k with xi_k ~ U[-1, 1] (Sec. 2.1, eq.
+ * (truncated-KLE)) and orthonormal Legendre chaos of total degree p (Sec. 2.2).
+ *
+ * Data layout of every block vector ("N x P, node-major"): N = (n-1)^2
+ * interior nodes numbered x-fastest, P = (m+p)!/(m!p!) chaos modes in graded
+ * order (by total degree; inside a degree by alpha_1 descending, then
+ * alpha_2 ...).  Element (node i, mode a) lives at index i*P + a.  Every degree
+ * level d is the contiguous column range [off[d], off[d+1]) of each row.
+ *
+ * Pointers: arguments documented as "device" are HIP device pointers that the
+ * caller allocates and owns (for instance torch tensors); "host" arguments are
+ * ordinary host memory.  The context owns everything else it allocates.
+ * Each context has one HIP stream (the one passed to sg_setup, or the null
+ * stream); all work is enqueued on it and calls return without waiting,
+ * except where a result is written to host memory.  A context is not
+ * thread-safe.
+ *
+ * Errors: every int-returning call returns 0 on success, a positive warning
+ * or a negative error code below; it never aborts.  sg_last_error() returns a
+ * message for the last failure in the calling thread.
+ */
+#ifndef SGBT_H
+#define SGBT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_OK 0
+#define SG_WNOTCOERCIVE 1 /* setup: min over cells of c_0 - sum_k |c_k| is <= 0 (A may be indefinite) */
+#define SG_EINVAL (-1)    /* invalid argument (sizes, null pointers, unsupported combination) */
+#define SG_ENOMEM (-2)    /* device or host allocation failed */
+#define SG_EHIP (-3)      /* a HIP runtime call failed; see sg_last_error() */
+#define SG_ENOTCONV (-4)  /* solver stopped at max_it above the tolerance (result still written) */
+#define SG_ENAN (-5)      /* a residual norm became NaN or Inf */
+
+/* precisions */
+#define SG_F64 0   /* all arithmetic and storage in double */
+#define SG_F32 1   /* float storage and float arithmetic (preconditioner-side variants only) */
+#define SG_MIXED 2 /* float preconditioner work, double Krylov / true residual (see each call) */
+
+/* smoother colourings for the multigrid V-cycle */
+#define SG_COLOUR_FOUR 0 /* colour (I mod 2) + 2 (J mod 2): exact Gauss-Seidel for the 9-point stencil */
+#define SG_COLOUR_RB 1   /* colour (I + J) mod 2, each colour updated from its start-of-colour values */
+
+typedef struct sg_ctx sg_ctx;
+
+typedef struct {
+    int n_cells;        /* n: cells per side; n = coarsest_cells * 2^L, n % 4 == 0, n <= 4096 */
+    int m;              /* KL terms, 0..8 */
+    int p;              /* total chaos degree, 0..8, with P = (m+p)!/(m!p!) <= 256 */
+    double sigma;       /* standard deviation scale of the field (Sec. 2.1, eq. (exponential-covariance)) */
+    double corr_len;    /* correlation length L > 0 */
+    int colour_mode;    /* SG_COLOUR_FOUR or SG_COLOUR_RB */
+    int nu1, nu2;       /* pre- and post-smoothing sweeps of the V-cycle, 0..8 */
+    int coarsest_cells; /* cells per side of the coarsest grid (>= 2); equal to n_cells gives exact K_0 solves */
+} sg_options;
+
+typedef struct {
+    int solver;   /* 0: right-preconditioned FGMRES(restart); 1: PCG (needs precond 0 and prec SG_F64) */
+    int precond;  /* 0: block-diagonal B_D (Sec. 4.1); 1: block-triangular B_T (Sec. 4.2) */
+    int prec;     /* SG_F64: double V-cycles; SG_MIXED: float V-cycles, double Krylov and residuals */
+    int restart;  /* FGMRES restart length, 1..64 */
+    int max_it;   /* maximum total iterations */
+    double rtol;  /* stop when ||F - A U||_2 / ||F||_2 < rtol (true residual, double) */
+    int use_x0;   /* 0: start from U = 0; 1: U holds the initial guess */
+    int timing;   /* 1: time the phases with HIP events (fills t_* below) */
+} sg_solve_opts;
+
+typedef struct {
+    int iters;              /* total Krylov iterations */
+    int restarts;           /* FGMRES cycles beyond the first */
+    int status;             /* return code of the solve */
+    int n_hist;             /* entries used in rel_res_hist */
+    double rel_res_true;    /* final ||F - A U|| / ||F|| in double */
+    double rel_res_hist[1024]; /* per-iteration residual estimate (recurrence), relative */
+    double t_total_ms;      /* wall time of the solve */
+    double t_apply_ms;      /* sum of operator-apply kernel times (timing = 1) */
+    double t_prec_ms;       /* sum of preconditioner times (timing = 1) */
+    double t_orth_ms;       /* sum of orthogonalisation times (timing = 1) */
+    int n_apply;            /* operator applies timed */
+    int n_prec;             /* preconditioner applications */
+} sg_solve_info;
+
+/* Build a context: KL eigenpairs of the separable exponential covariance,
+ * chaos tables, cell coefficients, the multigrid hierarchy of K_0 (Galerkin
+ * coarse operators) and the coarsest-grid factorisation; uploads them to the
+ * current HIP device.  a0_nodal: host, (n+1)^2 nodal mean field x-fastest, or
+ * NULL for a0 = 1.  kl_amp: host, m amplitudes s_k, or NULL for
+ * s_k = sqrt(lambda_k).  hip_stream: a hipStream_t or NULL.  Returns
+ * SG_WNOTCOERCIVE (ctx still valid) when the discrete coercivity margin is
+ * not positive. */
+int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp,
+             void* hip_stream, sg_ctx** out);
+
+/* Sizes and tables.  Any output pointer may be NULL.  level_offsets: host,
+ * p+2 ints; multi_index: host, P*m ints (row a = alpha of mode a);
+ * kl_lambda: host, m doubles; a_min_h: host, 1 double. */
+int sg_query(const sg_ctx* ctx, int* N, int* P, int* level_offsets, int* multi_index,
+             double* kl_lambda, double* a_min_h);
+
+/* Host copy of the cell coefficients c_{k,e} (Sec. 3.1, eq. (def-stiffness)
+ * with cell-constant coefficients): (m+1) rows of n*n cells, cell (cx, cy) at
+ * cy*n + cx.  out: host, (m+1)*n*n doubles. */
+int sg_get_cell_coeffs(const sg_ctx* ctx, double* out);
+
+/* F = e_0 (x) f_h for f = 1 (Sec. 2.2 Galerkin right-hand side). F: device, N*P doubles. */
+int sg_rhs(sg_ctx* ctx, double* F);
+
+/* Y = A U, matrix-free (Sec. 3.1, eq. (tensor-product)).
+ * prec SG_F64: U, Y device doubles.  SG_MIXED: U device floats, Y device
+ * doubles, double arithmetic.  U and Y must not overlap. */
+int sg_apply(sg_ctx* ctx, const void* U, void* Y, int prec);
+
+/* R = F - A U in one pass, all device doubles (true residual). */
+int sg_residual(sg_ctx* ctx, const double* F, const double* U, double* R);
+
+/* One batched V-cycle for K_0 (Sec. 4.1, Sec. 6) on `width` right-hand sides:
+ * u approximately K_0^{-1} f, zero initial guess.  f, u: device, N x width
+ * node-major with row strides ldf, ldu (elements).  prec SG_F64: doubles;
+ * SG_F32: floats.  1 <= width <= P. */
+int sg_vcycle(sg_ctx* ctx, const void* f, int ldf, void* u, int ldu, int width, int prec);
+
+/* Z = B_D^{-1} R with every K_0 solve replaced by one V-cycle (Sec. 4.1).
+ * prec SG_F64: R, Z device doubles.  SG_MIXED: R device doubles, Z device floats. */
+int sg_precond_diag(sg_ctx* ctx, const void* R, void* Z, int prec);
+
+/* Z = B_T^{-1} R: forward block Gauss-Seidel sweep over degree levels with
+ * one V-cycle per diagonal block (Sec. 4.2).  Precisions as sg_precond_diag. */
+int sg_precond_tri(sg_ctx* ctx, const void* R, void* Z, int prec);
+
+/* Solve A U = F (Sec. 4.2 with Sec. 6 stopping rule).  F, U: device doubles
+ * (U holds x0 if opts->use_x0).  info: host, may be NULL.  Returns SG_OK,
+ * SG_ENOTCONV or SG_ENAN (U holds the last iterate) or an error. */
+int sg_solve(sg_ctx* ctx, const double* F, double* U, const sg_solve_opts* opts, sg_solve_info* info);
+
+/* QoI of eq. (PCE_u) statistics: q_a = w_S . U_a with w_S the exact
+ * integration weights of S = [1/4, 3/4]^2 divided by |S|, and
+ * J = q_0 + sum_{a>0} q_a^2 (mean plus variance of the subdomain mean).
+ * U: device doubles.  q: host, P doubles (may be NULL).  J: host. */
+int sg_qoi(sg_ctx* ctx, const double* U, double* q, double* J);
+
+/* Adjoint gradient of J at the solution U: solves A lambda = dJ/dU with the
+ * same solver options, then dJ/dc_{k,e} = -sum G_k(a,b) lambda_{a,e}^T K_ref U_{b,e}
+ * and the chain rule to sigma, the KL amplitudes s_k and the interior nodal
+ * values of a0.  U: device doubles (a converged solution).  Outputs host:
+ * J (1), dJ_dsigma (1), dJ_damp (m), dJ_da0 ((n-1)^2, interior nodes x-fastest).
+ * adj_info: host, may be NULL. */
+int sg_qoi_grad(sg_ctx* ctx, const double* U, const sg_solve_opts* opts, double* J,
+                double* dJ_dsigma, double* dJ_damp, double* dJ_da0, sg_solve_info* adj_info);
+
+/* Host-only run of the setup arithmetic of sg_setup, without any device:
+ * for checking the tables on machines without a GPU.  Outputs (host, each may
+ * be NULL): cell_coeffs (m+1)*n*n as sg_get_cell_coeffs; fine_stencil N*9 and
+ * level1_stencil N_1*9 (9-point rows of K_0 and of its first Galerkin coarse
+ * operator, (dy,dx) row-major, N_1 = (n/2-1)^2, left untouched when the fine
+ * grid is the coarsest); coarsest_inverse Nc*Nc (row-major inverse of the
+ * coarsest operator); kl_lambda m; a_min_h 1. */
+int sg_setup_host(const sg_options* opt, const double* a0_nodal, const double* kl_amp, double* cell_coeffs,
+                  double* fine_stencil, double* level1_stencil, double* coarsest_inverse, double* kl_lambda,
+                  double* a_min_h);
+
+/* Wait for all work enqueued on the context's stream. */
+int sg_sync(sg_ctx* ctx);
+
+/* Release the context and its device memory. */
+void sg_destroy(sg_ctx* ctx);
+
+/* Message for the last failure in this thread ("" if none). */
+const char* sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGBT_H */

@@ -1,0 +1,698 @@
+// C ABI of libsgbt: context setup, the operator, the block preconditioners,
+// the Krylov drivers and the adjoint QoI gradient.  Host code here only
+// enqueues kernels on the context's stream and runs the O(restart^2) scalar
+// work of the Krylov recurrences (Hessenberg, Givens rotations).
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sg_internal.h"
+#include "sg_vec.h"
+
+namespace sg {
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename T>
+int dalloc(sg_ctx* c, T** p, size_t count) {
+    void* q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+        return SG_ENOMEM;
+    }
+    c->allocations.push_back(q);
+    *p = (T*)q;
+    return SG_OK;
+}
+
+template <typename T>
+int upload(sg_ctx* c, T** p, const std::vector<T>& host) {
+    int rc = dalloc(c, p, host.size());
+    if (rc) return rc;
+    SG_HIP_CHECK(hipMemcpy(*p, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+    return SG_OK;
+}
+
+int upload_plan(sg_ctx* c, const PlanHost& ph, Plan& pl) {
+    pl.in_lo = ph.in_lo;
+    pl.W_in = ph.W_in;
+    pl.out_lo = ph.out_lo;
+    pl.W_out = ph.W_out;
+    pl.nslot = ph.nslot;
+    pl.self = ph.self;
+    int rc = upload(c, &pl.d_off, ph.off);
+    if (rc) return rc;
+    return upload(c, &pl.d_coef, ph.coef);
+}
+
+size_t NP(const sg_ctx* c) { return (size_t)c->hs.N * c->hs.P; }
+
+int ensure_mg(sg_ctx* c, int is_float) {
+    const int P = c->hs.P;
+    for (size_t l = 0; l < c->levels.size(); ++l) {
+        Level& lv = c->levels[l];
+        const size_t cap = (size_t)lv.N * P;
+        int rc = SG_OK;
+        if (is_float && !lv.r32) {
+            rc = dalloc(c, &lv.r32, cap);
+            if (!rc && l > 0) rc = dalloc(c, &lv.u32, cap);
+            if (!rc && l > 0) rc = dalloc(c, &lv.f32, cap);
+        }
+        if (!is_float && !lv.r64) {
+            rc = dalloc(c, &lv.r64, cap);
+            if (!rc && l > 0) rc = dalloc(c, &lv.u64, cap);
+            if (!rc && l > 0) rc = dalloc(c, &lv.f64, cap);
+        }
+        if (rc) return rc;
+    }
+    if (!c->ws.fstage) {
+        c->ws.fstage_bytes = NP(c) * sizeof(double);
+        double* p = nullptr;
+        int rc = dalloc(c, &p, NP(c));
+        if (rc) return rc;
+        c->ws.fstage = p;
+    }
+    return SG_OK;
+}
+
+int ensure_scalars(sg_ctx* c) {
+    if (c->ws.scal) return SG_OK;
+    int rc = dalloc(c, &c->ws.scal, 1024);
+    if (rc) return rc;
+    rc = dalloc(c, &c->ws.partial, (size_t)kRedBlocks * 256);
+    if (rc) return rc;
+    SG_HIP_CHECK(hipHostMalloc((void**)&c->ws.host_scal, 1024 * sizeof(double), hipHostMallocDefault));
+    return SG_OK;
+}
+
+int ensure_krylov(sg_ctx* c, int restart, int z_float) {
+    int rc = ensure_scalars(c);
+    if (rc) return rc;
+    const size_t np = NP(c);
+    if (!c->ws.w) {
+        rc = dalloc(c, &c->ws.w, np);
+        if (rc) return rc;
+    }
+    if (c->ws.restart < restart) {
+        rc = dalloc(c, &c->ws.V, (size_t)(restart + 1) * np);
+        if (rc) return rc;
+        double* z = nullptr;  // sized for doubles, so it also holds a float basis
+        rc = dalloc(c, &z, (size_t)restart * np);
+        if (rc) return rc;
+        c->ws.Z = z;
+        c->ws.restart = restart;
+    }
+    c->ws.z_is_float = z_float;
+    return SG_OK;
+}
+
+// ------------------------------------------------------------------ preconditioners
+int precond_diag(sg_ctx* c, const double* R, void* Z, int zf) {
+    const int P = c->hs.P, N = c->hs.N;
+    int rc = ensure_mg(c, zf);
+    if (rc) return rc;
+    if (zf) {
+        rc = launch_cast(c->stream, R, 0, P, c->ws.fstage, 1, P, N, P);
+        if (rc) return rc;
+        return launch_vcycle(c, c->ws.fstage, P, Z, P, P, 1);
+    }
+    return launch_vcycle(c, R, P, Z, P, P, 0);
+}
+
+int precond_tri(sg_ctx* c, const double* R, void* Z, int zf) {
+    const int P = c->hs.P, N = c->hs.N, p = c->hs.p;
+    const auto& off = c->hs.offsets;
+    int rc = ensure_mg(c, zf);
+    if (rc) return rc;
+    const size_t es = zf ? sizeof(float) : sizeof(double);
+    for (int d = 0; d <= p; ++d) {
+        const int lo = off[d], Pd = off[d + 1] - off[d];
+        if (Pd == 0) continue;
+        const void* f;
+        int ldf;
+        if (d == 0) {
+            if (zf) {
+                rc = launch_cast(c->stream, R + lo, 0, P, c->ws.fstage, 1, Pd, N, Pd);
+                if (rc) return rc;
+                f = c->ws.fstage;
+                ldf = Pd;
+            } else {
+                f = R + lo;
+                ldf = P;
+            }
+        } else {
+            // R_d - sum_k [G_k]_{d,d-1} (x) K_k Z_{d-1}, into the staging block
+            const Plan& pl = c->plan_down[d];
+            const char* zin = (const char*)Z + (size_t)pl.in_lo * es;
+            rc = launch_apply(c, pl, zin, zf, R + lo, c->ws.fstage, zf, P, Pd, P);
+            if (rc) return rc;
+            f = c->ws.fstage;
+            ldf = Pd;
+        }
+        rc = launch_vcycle(c, f, ldf, (char*)Z + (size_t)lo * es, P, Pd, zf);
+        if (rc) return rc;
+    }
+    return SG_OK;
+}
+
+int apply_precond(sg_ctx* c, int kind, const double* R, void* Z, int zf) {
+    return kind == 1 ? precond_tri(c, R, Z, zf) : precond_diag(c, R, Z, zf);
+}
+
+// ------------------------------------------------------------------ Krylov
+struct Timer {
+    bool on = false;
+    hipEvent_t ev[6];
+    double apply = 0, prec = 0, orth = 0;
+    int napply = 0, nprec = 0;
+    void init(bool enable) {
+        on = enable;
+        if (on)
+            for (auto& e : ev) (void)hipEventCreate(&e);
+    }
+    void rec(int i, hipStream_t s) {
+        if (on) (void)hipEventRecord(ev[i], s);
+    }
+    void collect(bool had_prec, bool had_apply, bool had_orth) {
+        if (!on) return;
+        float ms;
+        if (had_prec && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) { prec += ms; ++nprec; }
+        if (had_apply && hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) { apply += ms; ++napply; }
+        if (had_orth && hipEventElapsedTime(&ms, ev[4], ev[5]) == hipSuccess) orth += ms;
+    }
+    void done() {
+        if (on)
+            for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+int fetch(sg_ctx* c, const double* dsrc, int count) {
+    SG_HIP_CHECK(hipMemcpyAsync(c->ws.host_scal, dsrc, count * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SG_HIP_CHECK(hipStreamSynchronize(c->stream));
+    return SG_OK;
+}
+
+int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_solve_info& info, Timer& tm) {
+    const size_t np = NP(c);
+    const int restart = o.restart;
+    const int zf = o.prec == SG_MIXED;
+    int rc = ensure_krylov(c, restart, zf);
+    if (rc) return rc;
+    double* scal = c->ws.scal;
+    double* hs = c->ws.host_scal;
+    const size_t zes = zf ? sizeof(float) : sizeof(double);
+    auto Vj = [&](int j) { return c->ws.V + (size_t)j * np; };
+    auto Zj = [&](int j) { return (void*)((char*)c->ws.Z + (size_t)j * np * zes); };
+
+    SG_HIP_CHECK(vec_dot(c->stream, F, F, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    const double nF = std::sqrt(hs[0]);
+    if (!(nF > 0.0) || !std::isfinite(nF)) {
+        if (nF == 0.0) {
+            info.rel_res_true = 0.0;
+            return launch_fill(c->stream, X, 0, 1, (int)np, 1);
+        }
+        set_error("right-hand side norm is not finite");
+        return SG_ENAN;
+    }
+    if (!o.use_x0 && (rc = launch_fill(c->stream, X, 0, 1, (int)np, 1))) return rc;
+    // r = F - A X
+    if ((rc = launch_apply(c, c->plan_full, X, 0, F, c->ws.w, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+    SG_HIP_CHECK(vec_dot(c->stream, c->ws.w, c->ws.w, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    double beta = std::sqrt(hs[0]);
+    info.rel_res_true = beta / nF;
+    if (!std::isfinite(beta)) {
+        set_error("initial residual is not finite");
+        return SG_ENAN;
+    }
+    if (beta / nF < o.rtol) return SG_OK;
+
+    std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
+    auto Hat = [&](int i, int j) -> double& { return H[(size_t)i * restart + j]; };
+    while (info.iters < o.max_it) {
+        SG_HIP_CHECK(vec_scale(c->stream, c->ws.w, 1.0 / beta, Vj(0), np));
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jlast = 0;
+        for (int j = 0; j < restart; ++j) {
+            tm.rec(0, c->stream);
+            if ((rc = apply_precond(c, o.precond, Vj(j), Zj(j), zf))) return rc;
+            tm.rec(1, c->stream);
+            tm.rec(2, c->stream);
+            if ((rc = launch_apply(c, c->plan_full, Zj(j), zf, nullptr, c->ws.w, 0, c->hs.P, c->hs.P, c->hs.P)))
+                return rc;
+            tm.rec(3, c->stream);
+            tm.rec(4, c->stream);
+            // classical Gram-Schmidt, twice
+            SG_HIP_CHECK(vec_multidot(c->stream, c->ws.V, np, j + 1, c->ws.w, np, c->ws.partial, scal));
+            SG_HIP_CHECK(vec_update(c->stream, c->ws.V, np, j + 1, scal, c->ws.w, np, nullptr, nullptr));
+            SG_HIP_CHECK(vec_multidot(c->stream, c->ws.V, np, j + 1, c->ws.w, np, c->ws.partial, scal + 128));
+            SG_HIP_CHECK(vec_update(c->stream, c->ws.V, np, j + 1, scal + 128, c->ws.w, np, c->ws.partial,
+                                    scal + 256));
+            tm.rec(5, c->stream);
+            SG_HIP_CHECK(hipMemcpyAsync(hs, scal, 257 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            SG_HIP_CHECK(hipStreamSynchronize(c->stream));
+            tm.collect(true, true, true);
+            for (int i = 0; i <= j; ++i) Hat(i, j) = hs[i] + hs[128 + i];
+            const double hn = std::sqrt(hs[256]);
+            if (!std::isfinite(hn)) {
+                set_error("Arnoldi vector norm is not finite");
+                return SG_ENAN;
+            }
+            Hat(j + 1, j) = hn;
+            const bool breakdown = hn == 0.0;
+            if (!breakdown) SG_HIP_CHECK(vec_scale(c->stream, c->ws.w, 1.0 / hn, Vj(j + 1), np));
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
+                Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
+                Hat(i, j) = t;
+            }
+            const double den = std::hypot(Hat(j, j), Hat(j + 1, j));
+            cs[j] = Hat(j, j) / den;
+            sn[j] = Hat(j + 1, j) / den;
+            Hat(j, j) = den;
+            Hat(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            info.iters++;
+            const double est = std::fabs(g[j + 1]) / nF;
+            if (info.n_hist < 1024) info.rel_res_hist[info.n_hist++] = est;
+            jlast = j;
+            if (est < o.rtol || breakdown || info.iters >= o.max_it) break;
+        }
+        const int k = jlast + 1;
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < k; ++l) s -= Hat(i, l) * y[l];
+            y[i] = s / Hat(i, i);
+        }
+        std::memcpy(hs + 512, y.data(), k * sizeof(double));
+        SG_HIP_CHECK(hipMemcpyAsync(scal + 512, hs + 512, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        SG_HIP_CHECK(vec_combine(c->stream, c->ws.Z, zf, np, k, scal + 512, X, np));
+        if ((rc = launch_apply(c, c->plan_full, X, 0, F, c->ws.w, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+        SG_HIP_CHECK(vec_dot(c->stream, c->ws.w, c->ws.w, np, c->ws.partial, scal));
+        if ((rc = fetch(c, scal, 1))) return rc;
+        beta = std::sqrt(hs[0]);
+        info.rel_res_true = beta / nF;
+        if (!std::isfinite(beta)) {
+            set_error("true residual is not finite");
+            return SG_ENAN;
+        }
+        if (beta / nF < o.rtol) return SG_OK;
+        if (info.iters >= o.max_it) break;
+        info.restarts++;
+    }
+    set_error("FGMRES reached max_it above the tolerance");
+    return SG_ENOTCONV;
+}
+
+int pcg(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_solve_info& info, Timer& tm) {
+    const size_t np = NP(c);
+    int rc = ensure_scalars(c);
+    if (rc) return rc;
+    if (!c->ws.pcg && (rc = dalloc(c, &c->ws.pcg, 4 * np))) return rc;
+    double *r = c->ws.pcg, *z = r + np, *p = z + np, *q = p + np;
+    double* scal = c->ws.scal;
+    double* hs = c->ws.host_scal;
+    SG_HIP_CHECK(vec_dot(c->stream, F, F, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    const double nF = std::sqrt(hs[0]);
+    if (nF == 0.0) return launch_fill(c->stream, X, 0, 1, (int)np, 1);
+    if (!o.use_x0 && (rc = launch_fill(c->stream, X, 0, 1, (int)np, 1))) return rc;
+    if ((rc = launch_apply(c, c->plan_full, X, 0, F, r, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+    SG_HIP_CHECK(vec_dot(c->stream, r, r, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    info.rel_res_true = std::sqrt(hs[0]) / nF;
+    if (info.rel_res_true < o.rtol) return SG_OK;
+    tm.rec(0, c->stream);
+    if ((rc = apply_precond(c, o.precond, r, z, 0))) return rc;
+    tm.rec(1, c->stream);
+    SG_HIP_CHECK(vec_scale(c->stream, z, 1.0, p, np));
+    SG_HIP_CHECK(vec_dot(c->stream, r, z, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    tm.collect(true, false, false);
+    double rz = hs[0];
+    while (info.iters < o.max_it) {
+        tm.rec(2, c->stream);
+        if ((rc = launch_apply(c, c->plan_full, p, 0, nullptr, q, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+        tm.rec(3, c->stream);
+        SG_HIP_CHECK(vec_dot(c->stream, p, q, np, c->ws.partial, scal));
+        if ((rc = fetch(c, scal, 1))) return rc;
+        tm.collect(false, true, false);
+        const double alpha = rz / hs[0];
+        SG_HIP_CHECK(vec_axpy(c->stream, alpha, p, X, np));
+        SG_HIP_CHECK(vec_axpy_sq(c->stream, -alpha, q, r, np, c->ws.partial, scal));
+        if ((rc = fetch(c, scal, 1))) return rc;
+        info.iters++;
+        const double rel = std::sqrt(hs[0]) / nF;
+        if (!std::isfinite(rel)) {
+            set_error("PCG residual is not finite");
+            return SG_ENAN;
+        }
+        if (info.n_hist < 1024) info.rel_res_hist[info.n_hist++] = rel;
+        if (rel < o.rtol) {
+            if ((rc = launch_apply(c, c->plan_full, X, 0, F, q, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+            SG_HIP_CHECK(vec_dot(c->stream, q, q, np, c->ws.partial, scal));
+            if ((rc = fetch(c, scal, 1))) return rc;
+            info.rel_res_true = std::sqrt(hs[0]) / nF;
+            if (info.rel_res_true < o.rtol) return SG_OK;
+        }
+        tm.rec(0, c->stream);
+        if ((rc = apply_precond(c, o.precond, r, z, 0))) return rc;
+        tm.rec(1, c->stream);
+        SG_HIP_CHECK(vec_dot(c->stream, r, z, np, c->ws.partial, scal));
+        if ((rc = fetch(c, scal, 1))) return rc;
+        tm.collect(true, false, false);
+        const double rzn = hs[0];
+        SG_HIP_CHECK(vec_xpby(c->stream, z, rzn / rz, p, np));
+        rz = rzn;
+    }
+    if ((rc = launch_apply(c, c->plan_full, X, 0, F, q, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+    SG_HIP_CHECK(vec_dot(c->stream, q, q, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    info.rel_res_true = std::sqrt(hs[0]) / nF;
+    set_error("PCG reached max_it above the tolerance");
+    return SG_ENOTCONV;
+}
+
+int check_opts(const sg_ctx* c, const sg_solve_opts* o) {
+    if (!o) return SG_EINVAL;
+    if (o->solver != 0 && o->solver != 1) return SG_EINVAL;
+    if (o->precond != 0 && o->precond != 1) return SG_EINVAL;
+    if (o->prec != SG_F64 && o->prec != SG_MIXED) return SG_EINVAL;
+    if (o->solver == 0 && (o->restart < 1 || o->restart > kMaxRestart)) return SG_EINVAL;
+    if (o->solver == 1 && (o->precond != 0 || o->prec != SG_F64)) return SG_EINVAL;
+    if (o->max_it < 1 || !(o->rtol > 0.0)) return SG_EINVAL;
+    (void)c;
+    return SG_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+const char* sg_last_error(void) { return g_last_error.c_str(); }
+
+int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp, void* hip_stream, sg_ctx** out) {
+    if (!opt || !out) {
+        set_error("sg_setup: null argument");
+        return SG_EINVAL;
+    }
+    *out = nullptr;
+    const int n = opt->n_cells, nc = opt->coarsest_cells;
+    if (n < 4 || n > 4096 || n % 4 != 0 || opt->m < 0 || opt->m > kMaxM || opt->p < 0 || opt->p > 8 || nc < 2 ||
+        nc > n || n % nc != 0 || ((n / nc) & (n / nc - 1)) != 0 || (nc - 1) * (nc - 1) > 4096 ||
+        !(opt->corr_len > 0.0) || opt->nu1 < 0 || opt->nu1 > 8 || opt->nu2 < 0 || opt->nu2 > 8 ||
+        (opt->colour_mode != SG_COLOUR_FOUR && opt->colour_mode != SG_COLOUR_RB) || !std::isfinite(opt->sigma)) {
+        set_error("sg_setup: invalid options (need n % 4 == 0, n = coarsest * 2^L, m <= 8, p <= 8, ...)");
+        return SG_EINVAL;
+    }
+    {
+        // P = (m+p)!/(m!p!) must fit 4 slots of 64 lanes
+        double Pd = 1.0;
+        for (int i = 1; i <= opt->p; ++i) Pd = Pd * (opt->m + i) / i;
+        if (Pd > 256.5) {
+            set_error("sg_setup: P = (m+p)!/(m!p!) exceeds 256");
+            return SG_EINVAL;
+        }
+    }
+    sg_ctx* c = new sg_ctx();
+    c->opt = *opt;
+    c->stream = (hipStream_t)hip_stream;
+    int warn = host_setup(*opt, a0_nodal, kl_amp, c->hs);
+    if (warn < 0) {
+        delete c;
+        return warn;
+    }
+    int rc = SG_OK;
+    auto fail = [&](int code) {
+        sg_destroy(c);
+        return code;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        set_error("sg_setup: no HIP device");
+        return fail(SG_EHIP);
+    }
+    const HostSetup& hs = c->hs;
+    const int m = hs.m, P = hs.P;
+    const size_t ncell = (size_t)n * n;
+    {
+        std::vector<double> cm(ncell * (m + 1)), kl(ncell * std::max(m, 1));
+        for (size_t e = 0; e < ncell; ++e) {
+            for (int k = 0; k <= m; ++k) cm[e * (m + 1) + k] = hs.cellc[(size_t)k * ncell + e] / 6.0;
+            for (int k = 0; k < m; ++k) kl[e * m + k] = hs.klcell[(size_t)k * ncell + e];
+        }
+        if ((rc = upload(c, &c->cell64, cm))) return fail(rc);
+        if ((rc = upload(c, &c->klcell, kl))) return fail(rc);
+    }
+    if ((rc = upload(c, &c->kinv, hs.coarse_inv))) return fail(rc);
+    c->levels.resize(hs.mg_n.size());
+    for (size_t l = 0; l < hs.mg_n.size(); ++l) {
+        Level& lv = c->levels[l];
+        std::memset(&lv, 0, sizeof(Level));
+        lv.n = hs.mg_n[l];
+        lv.nx = lv.n - 1;
+        lv.N = lv.nx * lv.nx;
+        if ((rc = upload(c, &lv.sten64, hs.mg_sten[l]))) return fail(rc);
+        std::vector<float> s32(hs.mg_sten[l].begin(), hs.mg_sten[l].end());
+        if ((rc = upload(c, &lv.sten32, s32))) return fail(rc);
+    }
+    if ((rc = upload_plan(c, make_plan(hs, 0, P, 0, P, true, true, true), c->plan_full))) return fail(rc);
+    c->plan_down.assign(hs.p + 1, Plan{});
+    for (int d = 1; d <= hs.p; ++d) {
+        const int lo = hs.offsets[d], Pd = hs.offsets[d + 1] - lo;
+        const int plo = hs.offsets[d - 1], Pp = hs.offsets[d] - plo;
+        if ((rc = upload_plan(c, make_plan(hs, plo, Pp, lo, Pd, false, false, true), c->plan_down[d])))
+            return fail(rc);
+    }
+    {
+        // QoI weights: exact integral of each interior hat function over
+        // S = [1/4, 3/4]^2, divided by |S| (grid aligned because n % 4 == 0)
+        const int nx = n - 1, a = n / 4, b = 3 * n / 4;
+        const double hh = 1.0 / n;
+        std::vector<double> w1(nx), wS((size_t)nx * nx);
+        for (int i = 1; i <= nx; ++i) w1[i - 1] = (i > a && i < b) ? hh : ((i == a || i == b) ? 0.5 * hh : 0.0);
+        for (int y = 0; y < nx; ++y)
+            for (int x = 0; x < nx; ++x) wS[(size_t)y * nx + x] = w1[x] * w1[y] * 4.0;
+        if ((rc = upload(c, &c->ws.wS, wS))) return fail(rc);
+        std::vector<double> amps(hs.amps);
+        amps.resize(std::max(m, 1), 0.0);
+        double* d_amps = nullptr;
+        if ((rc = upload(c, &d_amps, amps))) return fail(rc);
+        c->ws.amps = d_amps;
+    }
+    *out = c;
+    return warn;
+}
+
+int sg_query(const sg_ctx* c, int* N, int* P, int* level_offsets, int* multi_index, double* kl_lambda,
+             double* a_min_h) {
+    if (!c) {
+        set_error("sg_query: null context");
+        return SG_EINVAL;
+    }
+    if (N) *N = c->hs.N;
+    if (P) *P = c->hs.P;
+    if (level_offsets) std::memcpy(level_offsets, c->hs.offsets.data(), c->hs.offsets.size() * sizeof(int));
+    if (multi_index && c->hs.m) std::memcpy(multi_index, c->hs.midx.data(), c->hs.midx.size() * sizeof(int));
+    if (kl_lambda && c->hs.m) std::memcpy(kl_lambda, c->hs.lambda.data(), c->hs.m * sizeof(double));
+    if (a_min_h) *a_min_h = c->hs.a_min_h;
+    return SG_OK;
+}
+
+int sg_get_cell_coeffs(const sg_ctx* c, double* out) {
+    if (!c || !out) {
+        set_error("sg_get_cell_coeffs: null argument");
+        return SG_EINVAL;
+    }
+    std::memcpy(out, c->hs.cellc.data(), c->hs.cellc.size() * sizeof(double));
+    return SG_OK;
+}
+
+int sg_rhs(sg_ctx* c, double* F) {
+    if (!c || !F) {
+        set_error("sg_rhs: null argument");
+        return SG_EINVAL;
+    }
+    const double h = 1.0 / c->hs.n;
+    SG_HIP_CHECK(vec_rhs(c->stream, F, c->hs.N, c->hs.P, h * h));
+    return SG_OK;
+}
+
+int sg_apply(sg_ctx* c, const void* U, void* Y, int prec) {
+    if (!c || !U || !Y || (prec != SG_F64 && prec != SG_MIXED)) {
+        set_error("sg_apply: invalid argument");
+        return SG_EINVAL;
+    }
+    const int P = c->hs.P;
+    return launch_apply(c, c->plan_full, U, prec == SG_MIXED, nullptr, Y, 0, P, P, P);
+}
+
+int sg_residual(sg_ctx* c, const double* F, const double* U, double* R) {
+    if (!c || !F || !U || !R) {
+        set_error("sg_residual: null argument");
+        return SG_EINVAL;
+    }
+    const int P = c->hs.P;
+    return launch_apply(c, c->plan_full, U, 0, F, R, 0, P, P, P);
+}
+
+int sg_vcycle(sg_ctx* c, const void* f, int ldf, void* u, int ldu, int width, int prec) {
+    if (!c || !f || !u || width < 1 || width > c->hs.P || ldf < width || ldu < width ||
+        (prec != SG_F64 && prec != SG_F32)) {
+        set_error("sg_vcycle: invalid argument");
+        return SG_EINVAL;
+    }
+    int rc = ensure_mg(c, prec == SG_F32);
+    if (rc) return rc;
+    return launch_vcycle(c, f, ldf, u, ldu, width, prec == SG_F32);
+}
+
+int sg_precond_diag(sg_ctx* c, const void* R, void* Z, int prec) {
+    if (!c || !R || !Z || (prec != SG_F64 && prec != SG_MIXED)) {
+        set_error("sg_precond_diag: invalid argument");
+        return SG_EINVAL;
+    }
+    return precond_diag(c, (const double*)R, Z, prec == SG_MIXED);
+}
+
+int sg_precond_tri(sg_ctx* c, const void* R, void* Z, int prec) {
+    if (!c || !R || !Z || (prec != SG_F64 && prec != SG_MIXED)) {
+        set_error("sg_precond_tri: invalid argument");
+        return SG_EINVAL;
+    }
+    return precond_tri(c, (const double*)R, Z, prec == SG_MIXED);
+}
+
+int sg_solve(sg_ctx* c, const double* F, double* U, const sg_solve_opts* opts, sg_solve_info* info_out) {
+    if (!c || !F || !U || check_opts(c, opts) != SG_OK) {
+        set_error("sg_solve: invalid argument or options");
+        return SG_EINVAL;
+    }
+    sg_solve_info info;
+    std::memset(&info, 0, sizeof(info));
+    Timer tm;
+    tm.init(opts->timing != 0);
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = opts->solver == 0 ? fgmres(c, F, U, *opts, info, tm) : pcg(c, F, U, *opts, info, tm);
+    if (hipStreamSynchronize(c->stream) != hipSuccess && rc == SG_OK) {
+        set_error("sg_solve: stream synchronisation failed");
+        rc = SG_EHIP;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    info.t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    info.t_apply_ms = tm.apply;
+    info.t_prec_ms = tm.prec;
+    info.t_orth_ms = tm.orth;
+    info.n_apply = tm.napply;
+    info.n_prec = tm.nprec;
+    info.status = rc;
+    tm.done();
+    if (info_out) *info_out = info;
+    return rc;
+}
+
+int sg_qoi(sg_ctx* c, const double* U, double* q, double* J) {
+    if (!c || !U || !J) {
+        set_error("sg_qoi: null argument");
+        return SG_EINVAL;
+    }
+    int rc = ensure_scalars(c);
+    if (rc) return rc;
+    const int P = c->hs.P;
+    if (!c->ws.qv && (rc = dalloc(c, &c->ws.qv, 2 * (size_t)P + 8))) return rc;
+    SG_HIP_CHECK(vec_qoi(c->stream, U, c->ws.wS, c->hs.N, P, c->ws.partial, c->ws.qv, c->ws.qv + 2 * P,
+                         c->ws.qv + P));
+    SG_HIP_CHECK(hipMemcpyAsync(c->ws.host_scal, c->ws.qv, (2 * P + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+    SG_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (q) std::memcpy(q, c->ws.host_scal, P * sizeof(double));
+    *J = c->ws.host_scal[2 * P];
+    return SG_OK;
+}
+
+int sg_qoi_grad(sg_ctx* c, const double* U, const sg_solve_opts* opts, double* J, double* dJ_dsigma, double* dJ_damp,
+                double* dJ_da0, sg_solve_info* adj_info) {
+    if (!c || !U || !J || !dJ_dsigma || (!dJ_damp && c->hs.m) || !dJ_da0 || check_opts(c, opts) != SG_OK) {
+        set_error("sg_qoi_grad: invalid argument");
+        return SG_EINVAL;
+    }
+    int rc = sg_qoi(c, U, nullptr, J);
+    if (rc) return rc;
+    const size_t np = NP(c);
+    const int n = c->hs.n, m = c->hs.m, P = c->hs.P, N = c->hs.N;
+    if (!c->ws.lam && (rc = dalloc(c, &c->ws.lam, np))) return rc;
+    if (!c->ws.g && (rc = dalloc(c, &c->ws.g, np))) return rc;
+    if (!c->ws.dc && (rc = dalloc(c, &c->ws.dc, (size_t)n * n * (m + 1) + 16 + (size_t)N))) return rc;
+    SG_HIP_CHECK(vec_adj_rhs(c->stream, c->ws.wS, c->ws.qv + P, N, P, c->ws.g));
+    sg_solve_opts o = *opts;
+    o.use_x0 = 0;
+    rc = sg_solve(c, c->ws.g, c->ws.lam, &o, adj_info);
+    if (rc < 0) return rc;
+    SG_HIP_CHECK(vec_grad_cells(c->stream, c->plan_full.nslot, U, c->ws.lam, n, P, m, c->plan_full.d_off,
+                                c->plan_full.d_coef, c->ws.dc));
+    double* params = c->ws.scal + 600;  // 1 + m values
+    double* Tk = c->ws.scal + 700;
+    double* a0 = c->ws.dc + (size_t)n * n * (m + 1) + 16;
+    SG_HIP_CHECK(vec_grad_params(c->stream, c->ws.dc, c->klcell, c->ws.amps, c->opt.sigma, n, m, c->ws.partial, Tk,
+                                 params, a0));
+    SG_HIP_CHECK(hipMemcpyAsync(c->ws.host_scal + 600, params, (1 + m) * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+    SG_HIP_CHECK(hipMemcpyAsync(dJ_da0, a0, (size_t)N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SG_HIP_CHECK(hipStreamSynchronize(c->stream));
+    *dJ_dsigma = c->ws.host_scal[600];
+    for (int k = 0; k < m; ++k) dJ_damp[k] = c->ws.host_scal[601 + k];
+    return SG_OK;
+}
+
+int sg_setup_host(const sg_options* opt, const double* a0_nodal, const double* kl_amp, double* cell_coeffs,
+                  double* fine_stencil, double* level1_stencil, double* coarsest_inverse, double* kl_lambda,
+                  double* a_min_h) {
+    if (!opt || opt->n_cells < 4 || opt->n_cells > 4096 || opt->n_cells % 4 || opt->m < 0 || opt->m > kMaxM ||
+        opt->p < 0 || opt->p > 8 || opt->coarsest_cells < 2 || opt->coarsest_cells > opt->n_cells ||
+        opt->n_cells % opt->coarsest_cells || !(opt->corr_len > 0.0)) {
+        set_error("sg_setup_host: invalid options");
+        return SG_EINVAL;
+    }
+    HostSetup hs;
+    const int rc = host_setup(*opt, a0_nodal, kl_amp, hs);
+    if (rc < 0) return rc;
+    if (cell_coeffs) std::memcpy(cell_coeffs, hs.cellc.data(), hs.cellc.size() * sizeof(double));
+    if (fine_stencil) std::memcpy(fine_stencil, hs.mg_sten[0].data(), hs.mg_sten[0].size() * sizeof(double));
+    if (level1_stencil && hs.mg_sten.size() > 1)
+        std::memcpy(level1_stencil, hs.mg_sten[1].data(), hs.mg_sten[1].size() * sizeof(double));
+    if (coarsest_inverse) std::memcpy(coarsest_inverse, hs.coarse_inv.data(), hs.coarse_inv.size() * sizeof(double));
+    if (kl_lambda && hs.m) std::memcpy(kl_lambda, hs.lambda.data(), hs.m * sizeof(double));
+    if (a_min_h) *a_min_h = hs.a_min_h;
+    return rc;
+}
+
+int sg_sync(sg_ctx* c) {
+    if (!c) return SG_EINVAL;
+    SG_HIP_CHECK(hipStreamSynchronize(c->stream));
+    return SG_OK;
+}
+
+void sg_destroy(sg_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (void* p : c->allocations) (void)hipFree(p);
+    if (c->ws.host_scal) (void)hipHostFree(c->ws.host_scal);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Internal declarations shared by the host setup, the kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sgbt.h"
+
+namespace sg {
+
+constexpr int kMaxM = 8;
+constexpr int kMaxSlots = 4;  // modes per node handled by one wave: up to 4 x 64 = 256
+constexpr int kMaxRestart = 64;
+
+void set_error(const std::string& msg);
+
+#define SG_HIP_CHECK(expr)                                                          \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            ::sg::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));      \
+            return SG_EHIP;                                                         \
+        }                                                                           \
+    } while (0)
+
+// ---------------------------------------------------------------- host setup
+struct HostSetup {
+    int n = 0, m = 0, p = 0, P = 0, N = 0;
+    std::vector<int> offsets;          // p+2
+    std::vector<int> midx;             // P*m
+    std::vector<double> lambda;        // m eigenvalues lambda_k of the 2-D modes
+    std::vector<double> amps;          // m amplitudes s_k
+    std::vector<double> cellc;         // (m+1) x n*n, row k
+    std::vector<double> klcell;        // m x n*n values b_k at cell centres
+    double a_min_h = 0.0;
+    // multigrid, level 0 = finest
+    std::vector<int> mg_n;             // cells per side per level
+    std::vector<std::vector<double>> mg_sten;  // per level: N_l x 9, (dy,dx) row-major
+    std::vector<double> coarse_inv;    // N_c x N_c inverse of the coarsest operator
+};
+
+int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_amp, HostSetup& hs);
+
+// coupling tables of one apply "plan": output modes [out_lo, out_lo+W_out),
+// input modes [in_lo, in_lo+W_in).  For each output lane-slot and k:
+// packed LDS element indices (up | dn << 16) and coefficients (up, dn).
+struct PlanHost {
+    int in_lo = 0, W_in = 0, out_lo = 0, W_out = 0, nslot = 1;
+    int self = 0;  // include the k = 0 (G_0 = I) term
+    std::vector<uint32_t> off;   // nslot*64*m
+    std::vector<double> coef;    // nslot*64*m*2
+};
+PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_out, bool self, bool up, bool down);
+
+// ---------------------------------------------------------------- device side
+struct Plan {
+    int in_lo, W_in, out_lo, W_out, nslot, self;
+    uint32_t* d_off;
+    double* d_coef;
+};
+
+struct Level {
+    int n, nx, N;          // cells, interior nodes per side, interior nodes
+    double* sten64;        // N x 9
+    float* sten32;
+    // work buffers, capacity N x P
+    double* u64; double* f64; double* r64;
+    float* u32; float* f32; float* r32;
+};
+
+struct Workspace {
+    // Krylov
+    int restart = 0;
+    double* V = nullptr;         // (restart+1) x NP
+    void* Z = nullptr;           // restart x NP, float (mixed) or double
+    int z_is_float = 0;
+    double* w = nullptr;         // NP
+    double* amps = nullptr;      // m KL amplitudes s_k
+    double* pcg = nullptr;       // 4 x NP (PCG r, z, p, q)
+    double* partial = nullptr;   // reduction partials
+    double* scal = nullptr;      // device scalars (h, norms, y)
+    double* host_scal = nullptr; // pinned mirror
+    // preconditioner staging
+    void* fstage = nullptr;      // N x P (float or double) right-hand side staging
+    size_t fstage_bytes = 0;
+    // adjoint
+    double* lam = nullptr;       // NP
+    double* g = nullptr;         // NP
+    double* dc = nullptr;        // n*n x (m+1)
+    double* wS = nullptr;        // N
+    double* qv = nullptr;        // P
+};
+
+}  // namespace sg
+
+struct sg_ctx {
+    sg::HostSetup hs;
+    sg_options opt;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // device data
+    double* cell64 = nullptr;   // n*n x (m+1), cell-major, pre-scaled by 1/6
+    double* klcell = nullptr;   // n*n x m  b_k at cell centres, cell-major
+    double* kinv = nullptr;     // N_c x N_c
+    std::vector<sg::Level> levels;
+    sg::Plan plan_full{};
+    std::vector<sg::Plan> plan_down;  // index d = 1..p
+    sg::Workspace ws;
+    std::vector<void*> allocations;
+};
+
+namespace sg {
+
+// kernel launchers (defined in the .hip files).  launch_apply takes U already
+// offset to the plan's first input mode and R, Y already offset to its first
+// output mode (Y may also be a compact buffer of width W_out).
+int launch_apply(sg_ctx* c, const Plan& pl, const void* U, int in_float, const double* R, void* Y,
+                 int out_float, int ldu, int ldy, int ldr);
+int launch_vcycle(sg_ctx* c, const void* f, int ldf, void* u, int ldu, int width, int is_float);
+int launch_cast(hipStream_t s, const void* src, int src_float, int lds, void* dst, int dst_float, int ldd,
+                int rows, int width);
+int launch_fill(hipStream_t s, void* dst, int is_float, int ld, int rows, int width);
+
+}  // namespace sg

@@ -1,0 +1,318 @@
+// Batched geometric multigrid V-cycle for the mean stiffness K_0.
+//
+// The paper inverts every diagonal block K_0 of B_D and B_T by one V-cycle
+// (Sec. 4.1, Sec. 4.2; Sec. 6 uses V(2,2) with point Gauss-Seidel).  All
+// diagonal blocks are the same K_0, so the cycle runs on many right-hand
+// sides at once: an N_l x W node-major block, with the W modes of a node
+// contiguous.  Threads are laid out (modes x nodes) so a node's stencil
+// (9 coefficients, Galerkin coarse operators from setup) is fetched once per
+// node and broadcast to the lanes of its modes, and every access to the
+// block is a contiguous run of W values.
+//
+// Components: multi-colour Gauss-Seidel (four colours (I mod 2, J mod 2), or
+// red/black with each colour updated from its start-of-colour values),
+// residual, full-weighting restriction R = P^T, bilinear prolongation P, and
+// the coarsest grid solved with the explicit inverse of its operator in
+// double precision.
+
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+struct Tile {
+    int tx, ty;
+};
+
+Tile tile_for(int width) {
+    int tx = 1;
+    while (tx < width && tx < 64) tx <<= 1;
+    return {tx, 256 / tx};
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ dst, int ld, int rows, int width) {
+    const int mode = blockIdx.y * blockDim.x + threadIdx.x;
+    const int row = blockIdx.x * blockDim.y + threadIdx.y;
+    if (mode < width && row < rows) dst[(size_t)row * ld + mode] = T(0);
+}
+
+template <typename Ts, typename Td>
+__global__ void k_cast(const Ts* __restrict__ src, int lds, Td* __restrict__ dst, int ldd, int rows, int width) {
+    const int mode = blockIdx.y * blockDim.x + threadIdx.x;
+    const int row = blockIdx.x * blockDim.y + threadIdx.y;
+    if (mode < width && row < rows) dst[(size_t)row * ldd + mode] = (Td)src[(size_t)row * lds + mode];
+}
+
+// Gauss-Seidel update of the nodes of one colour.  Colour lattice: nodes
+// (x0 + sx*i, y) with row-dependent start for red/black.
+//   four colours: px, py fixed parities, x = px + 2i, y = py + 2j
+//   red/black   : (x + y) & 1 == q, x = ((q + y) & 1) + 2i
+// snap == nullptr: in-place update (four colours never touch each other).
+// snap != nullptr: red/black first pass, new values are written to `snap`
+// (a staging buffer) and copied back by k_copy_colour.
+template <typename T>
+__global__ void k_gs(const T* __restrict__ sten, T* __restrict__ u, int ldu, const T* __restrict__ f, int ldf,
+                     T* __restrict__ out, int ldo, int nx, int width, int rb, int q, int nxc, int nyc) {
+    const int mode = blockIdx.y * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.y + threadIdx.y;
+    if (mode >= width || t >= nxc * nyc) return;
+    const int j = t / nxc, i = t - j * nxc;
+    int x, y;
+    if (rb) {
+        y = j;
+        x = ((q + y) & 1) + 2 * i;
+        if (x >= nx) return;
+    } else {
+        x = (((q & 1) ^ 1)) + 2 * i;
+        y = (((q >> 1) ^ 1)) + 2 * j;
+    }
+    const size_t node = (size_t)y * nx + x;
+    const T* st = sten + node * 9;
+    T acc = f[node * ldf + mode];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= nx) continue;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            const int xx = x + dx;
+            if (xx < 0 || xx >= nx) continue;
+            acc -= st[(dy + 1) * 3 + (dx + 1)] * u[((size_t)yy * nx + xx) * ldu + mode];
+        }
+    }
+    const T val = acc / st[4];
+    if (out)
+        out[node * ldo + mode] = val;
+    else
+        u[node * ldu + mode] = val;
+}
+
+template <typename T>
+__global__ void k_copy_colour(const T* __restrict__ src, int lds, T* __restrict__ u, int ldu, int nx, int width,
+                              int q, int nxc, int nyc) {
+    const int mode = blockIdx.y * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.y + threadIdx.y;
+    if (mode >= width || t >= nxc * nyc) return;
+    const int y = t / nxc, i = t - y * nxc;
+    const int x = ((q + y) & 1) + 2 * i;
+    if (x >= nx) return;
+    const size_t node = (size_t)y * nx + x;
+    u[node * ldu + mode] = src[node * lds + mode];
+}
+
+template <typename T>
+__global__ void k_residual(const T* __restrict__ sten, const T* __restrict__ u, int ldu, const T* __restrict__ f,
+                           int ldf, T* __restrict__ r, int ldr, int nx, int width) {
+    const int mode = blockIdx.y * blockDim.x + threadIdx.x;
+    const int node = blockIdx.x * blockDim.y + threadIdx.y;
+    if (mode >= width || node >= nx * nx) return;
+    const int y = node / nx, x = node - y * nx;
+    const T* st = sten + (size_t)node * 9;
+    T acc = f[(size_t)node * ldf + mode];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= nx) continue;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= nx) continue;
+            acc -= st[(dy + 1) * 3 + (dx + 1)] * u[((size_t)yy * nx + xx) * ldu + mode];
+        }
+    }
+    r[(size_t)node * ldr + mode] = acc;
+}
+
+// coarse node (X, Y) sits on fine node (2X+1, 2Y+1); weights 1, 1/2, 1/4
+template <typename T>
+__global__ void k_restrict(const T* __restrict__ r, int ldr, T* __restrict__ fc, int ldc, int nxc, int width) {
+    const int mode = blockIdx.y * blockDim.x + threadIdx.x;
+    const int node = blockIdx.x * blockDim.y + threadIdx.y;
+    if (mode >= width || node >= nxc * nxc) return;
+    const int Y = node / nxc, X = node - Y * nxc;
+    const int nxf = 2 * nxc + 1;
+    const int fx = 2 * X + 1, fy = 2 * Y + 1;
+    T acc = T(0);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const T wy = dy == 0 ? T(1) : T(0.5);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const T wx = dx == 0 ? T(1) : T(0.5);
+            acc += wx * wy * r[((size_t)(fy + dy) * nxf + (fx + dx)) * ldr + mode];
+        }
+    }
+    fc[(size_t)node * ldc + mode] = acc;
+}
+
+template <typename T>
+__global__ void k_prolong_add(const T* __restrict__ ec, int ldc, T* __restrict__ u, int ldu, int nxf, int width) {
+    const int mode = blockIdx.y * blockDim.x + threadIdx.x;
+    const int node = blockIdx.x * blockDim.y + threadIdx.y;
+    if (mode >= width || node >= nxf * nxf) return;
+    const int y = node / nxf, x = node - y * nxf;
+    const int nxc = (nxf - 1) / 2;
+    // fine x odd: on a coarse node (x-1)/2; x even: between coarse x/2-1 and x/2
+    int cx[2], cy[2], nxs, nys;
+    T wx, wy;
+    if (x & 1) { cx[0] = (x - 1) >> 1; nxs = 1; wx = T(1); }
+    else { cx[0] = (x >> 1) - 1; cx[1] = x >> 1; nxs = 2; wx = T(0.5); }
+    if (y & 1) { cy[0] = (y - 1) >> 1; nys = 1; wy = T(1); }
+    else { cy[0] = (y >> 1) - 1; cy[1] = y >> 1; nys = 2; wy = T(0.5); }
+    T acc = T(0);
+    for (int b = 0; b < nys; ++b) {
+        if (cy[b] < 0 || cy[b] >= nxc) continue;
+        for (int a = 0; a < nxs; ++a) {
+            if (cx[a] < 0 || cx[a] >= nxc) continue;
+            acc += ec[((size_t)cy[b] * nxc + cx[a]) * ldc + mode];
+        }
+    }
+    u[(size_t)node * ldu + mode] += wx * wy * acc;
+}
+
+// u = Kinv f for every column; one block per column, double arithmetic
+template <typename T>
+__global__ void k_coarse(const double* __restrict__ kinv, const T* __restrict__ f, int ldf, T* __restrict__ u,
+                         int ldu, int Nc) {
+    extern __shared__ double fs[];
+    const int col = blockIdx.x;
+    for (int i = threadIdx.x; i < Nc; i += blockDim.x) fs[i] = (double)f[(size_t)i * ldf + col];
+    __syncthreads();
+    for (int i = threadIdx.x; i < Nc; i += blockDim.x) {
+        const double* row = kinv + (size_t)i * Nc;
+        double acc = 0.0;
+        for (int j = 0; j < Nc; ++j) acc = fma(row[j], fs[j], acc);
+        u[(size_t)i * ldu + col] = (T)acc;
+    }
+}
+
+inline dim3 grid2(int rows, int width, const Tile& tl) {
+    return dim3((rows + tl.ty - 1) / tl.ty, (width + tl.tx - 1) / tl.tx);
+}
+
+template <typename T>
+struct LevelPtr;
+template <>
+struct LevelPtr<double> {
+    static double* u(Level& l) { return l.u64; }
+    static double* f(Level& l) { return l.f64; }
+    static double* r(Level& l) { return l.r64; }
+    static const double* s(const Level& l) { return l.sten64; }
+};
+template <>
+struct LevelPtr<float> {
+    static float* u(Level& l) { return l.u32; }
+    static float* f(Level& l) { return l.f32; }
+    static float* r(Level& l) { return l.r32; }
+    static const float* s(const Level& l) { return l.sten32; }
+};
+
+template <typename T>
+void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, bool reverse, const Tile& tl) {
+    Level& lv = c->levels[l];
+    const int nx = lv.nx;
+    const bool rb = c->opt.colour_mode == SG_COLOUR_RB;
+    const int ncol = rb ? 2 : 4;
+    for (int qi = 0; qi < ncol; ++qi) {
+        const int q = reverse ? ncol - 1 - qi : qi;
+        if (!rb) {
+            const int px = (q & 1) ^ 1, py = (q >> 1) ^ 1;
+            const int nxc = (nx - px + 1) / 2, nyc = (nx - py + 1) / 2;
+            hipLaunchKernelGGL(k_gs<T>, grid2(nxc * nyc, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                               LevelPtr<T>::s(lv), u, ldu, f, ldf, (T*)nullptr, 0, nx, width, 0, q, nxc, nyc);
+        } else {
+            const int nxc = (nx + 1) / 2, nyc = nx;
+            T* stage = LevelPtr<T>::r(lv);  // residual buffer is free during smoothing
+            hipLaunchKernelGGL(k_gs<T>, grid2(nxc * nyc, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                               LevelPtr<T>::s(lv), u, ldu, f, ldf, stage, width, nx, width, 1, q, nxc, nyc);
+            hipLaunchKernelGGL(k_copy_colour<T>, grid2(nxc * nyc, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                               (const T*)stage, width, u, ldu, nx, width, q, nxc, nyc);
+        }
+    }
+}
+
+template <typename T>
+int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
+    const Tile tl = tile_for(width);
+    const int L = (int)c->levels.size() - 1;
+    const size_t nc_sh = (size_t)c->levels[L].N * sizeof(double);
+    if (L == 0) {
+        hipLaunchKernelGGL(k_coarse<T>, dim3(width), dim3(256), nc_sh, c->stream, c->kinv, f0, ldf0, u0, ldu0,
+                           c->levels[0].N);
+        return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
+    }
+    for (int l = 0; l < L; ++l) {
+        Level& lv = c->levels[l];
+        const T* f = l == 0 ? f0 : LevelPtr<T>::f(lv);
+        const int ldf = l == 0 ? ldf0 : width;
+        T* u = l == 0 ? u0 : LevelPtr<T>::u(lv);
+        const int ldu = l == 0 ? ldu0 : width;
+        hipLaunchKernelGGL(k_fill<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream, u, ldu, lv.N, width);
+        for (int s = 0; s < c->opt.nu1; ++s) smooth<T>(c, l, u, ldu, f, ldf, width, false, tl);
+        T* r = LevelPtr<T>::r(lv);
+        hipLaunchKernelGGL(k_residual<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                           LevelPtr<T>::s(lv), (const T*)u, ldu, f, ldf, r, width, lv.nx, width);
+        Level& lc = c->levels[l + 1];
+        hipLaunchKernelGGL(k_restrict<T>, grid2(lc.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                           (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width);
+    }
+    {
+        Level& lc = c->levels[L];
+        hipLaunchKernelGGL(k_coarse<T>, dim3(width), dim3(256), nc_sh, c->stream, c->kinv,
+                           (const T*)LevelPtr<T>::f(lc), width, LevelPtr<T>::u(lc), width, lc.N);
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        Level& lv = c->levels[l];
+        const T* f = l == 0 ? f0 : LevelPtr<T>::f(lv);
+        const int ldf = l == 0 ? ldf0 : width;
+        T* u = l == 0 ? u0 : LevelPtr<T>::u(lv);
+        const int ldu = l == 0 ? ldu0 : width;
+        hipLaunchKernelGGL(k_prolong_add<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                           (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, ldu, lv.nx, width);
+        for (int s = 0; s < c->opt.nu2; ++s) smooth<T>(c, l, u, ldu, f, ldf, width, true, tl);
+    }
+    return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
+}
+
+}  // namespace
+
+int launch_vcycle(sg_ctx* c, const void* f, int ldf, void* u, int ldu, int width, int is_float) {
+    int rc = is_float ? vcycle_t<float>(c, (const float*)f, ldf, (float*)u, ldu, width)
+                      : vcycle_t<double>(c, (const double*)f, ldf, (double*)u, ldu, width);
+    if (rc != SG_OK) set_error("vcycle: kernel launch failed");
+    return rc;
+}
+
+int launch_cast(hipStream_t s, const void* src, int src_float, int lds, void* dst, int dst_float, int ldd, int rows,
+                int width) {
+    const Tile tl = tile_for(width);
+    if (src_float && dst_float)
+        hipLaunchKernelGGL((k_cast<float, float>), grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s,
+                           (const float*)src, lds, (float*)dst, ldd, rows, width);
+    else if (src_float)
+        hipLaunchKernelGGL((k_cast<float, double>), grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s,
+                           (const float*)src, lds, (double*)dst, ldd, rows, width);
+    else if (dst_float)
+        hipLaunchKernelGGL((k_cast<double, float>), grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s,
+                           (const double*)src, lds, (float*)dst, ldd, rows, width);
+    else
+        hipLaunchKernelGGL((k_cast<double, double>), grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s,
+                           (const double*)src, lds, (double*)dst, ldd, rows, width);
+    return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
+}
+
+int launch_fill(hipStream_t s, void* dst, int is_float, int ld, int rows, int width) {
+    const Tile tl = tile_for(width);
+    if (is_float)
+        hipLaunchKernelGGL(k_fill<float>, grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s, (float*)dst, ld, rows,
+                           width);
+    else
+        hipLaunchKernelGGL(k_fill<double>, grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s, (double*)dst, ld,
+                           rows, width);
+    return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
+}
+
+}  // namespace sg

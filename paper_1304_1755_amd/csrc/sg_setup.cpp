@@ -1,0 +1,350 @@
+// Host-side setup: KL eigenpairs, chaos tables, cell coefficients, the
+// multigrid hierarchy of K_0 and the coupling plans used by the apply kernels.
+// Runs once per context, in double precision.
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+namespace {
+
+// ------------------------------------------------------------------ KL (Sec. 2.1)
+// 1-D covariance exp(-c|s-t|) on t in [-1/2, 1/2].  Even eigenfunctions
+// cos(w t) need c cos(w/2) = w sin(w/2); odd ones sin(w t) need
+// w cos(w/2) = -c sin(w/2); the eigenvalue is 2c / (w^2 + c^2).  Each
+// equation has exactly one root per half period; it is isolated by bisection
+// down to adjacent doubles.
+struct Mode1D {
+    bool even;
+    double w, lam, norm;
+};
+
+double even_fn(double w, double c) { return c * std::cos(0.5 * w) - w * std::sin(0.5 * w); }
+double odd_fn(double w, double c) { return w * std::cos(0.5 * w) + c * std::sin(0.5 * w); }
+
+double bisect(double (*f)(double, double), double lo, double hi, double c) {
+    double flo = f(lo, c);
+    for (int it = 0; it < 2000; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double fm = f(mid, c);
+        if (fm == 0.0) return mid;
+        if ((fm > 0) == (flo > 0)) {
+            lo = mid;
+            flo = fm;
+        } else {
+            hi = mid;
+        }
+    }
+    return 0.5 * (lo + hi);
+}
+
+std::vector<Mode1D> kl_1d(double corr_len, int count) {
+    const double c = 1.0 / corr_len;
+    const double pi = 3.14159265358979323846;
+    std::vector<Mode1D> out;
+    for (int j = 0; (int)out.size() < count; ++j) {
+        double w = bisect(even_fn, 2 * j * pi, 2 * j * pi + pi, c);
+        out.push_back({true, w, 2 * c / (w * w + c * c), std::sqrt(0.5 + std::sin(w) / (2 * w))});
+        if ((int)out.size() == count) break;
+        w = bisect(odd_fn, 2 * j * pi + pi, 2 * j * pi + 2 * pi, c);
+        out.push_back({false, w, 2 * c / (w * w + c * c), std::sqrt(0.5 - std::sin(w) / (2 * w))});
+    }
+    return out;
+}
+
+double eval1d(const Mode1D& md, double t) {
+    return (md.even ? std::cos(md.w * t) : std::sin(md.w * t)) / md.norm;
+}
+
+// ------------------------------------------------------------------ chaos (Sec. 2.2, 3.1)
+// orthonormal Legendre recurrence: xi q_k = b_{k+1} q_{k+1} + b_k q_{k-1},
+// b_k = k / sqrt(4k^2 - 1); so E[xi q_a q_{a+1}] = b_{a+1}.
+double legendre_b(int k) { return k / std::sqrt(4.0 * k * k - 1.0); }
+
+std::vector<std::vector<int>> graded_indices(int m, int p) {
+    // enumerate every alpha in {0..p}^m with |alpha| <= p, then order by total
+    // degree and, inside a degree, by alpha_1 descending, alpha_2 descending, ...
+    std::vector<std::vector<int>> all;
+    std::vector<int> a(m, 0);
+    if (m == 0) {
+        all.push_back({});
+        return all;
+    }
+    while (true) {
+        int s = 0;
+        for (int v : a) s += v;
+        if (s <= p) all.push_back(a);
+        int i = 0;
+        while (i < m) {
+            if (++a[i] <= p) break;
+            a[i] = 0;
+            ++i;
+        }
+        if (i == m) break;
+    }
+    std::sort(all.begin(), all.end(), [](const std::vector<int>& x, const std::vector<int>& y) {
+        int sx = 0, sy = 0;
+        for (int v : x) sx += v;
+        for (int v : y) sy += v;
+        if (sx != sy) return sx < sy;
+        return x > y;  // lexicographically larger first
+    });
+    return all;
+}
+
+// ------------------------------------------------------------------ dense SPD helpers
+bool cholesky_inverse(std::vector<double>& A, int n) {
+    // A (n x n, row-major, symmetric) -> A^{-1} via A = L L^T
+    std::vector<double> L(A.size(), 0.0);
+    for (int j = 0; j < n; ++j) {
+        double d = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(d > 0)) return false;
+        double ljj = std::sqrt(d);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double s = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = s / ljj;
+        }
+    }
+    std::vector<double> inv((size_t)n * n, 0.0), col(n);
+    for (int c = 0; c < n; ++c) {
+        for (int i = 0; i < n; ++i) {  // forward: L y = e_c
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * col[k];
+            col[i] = s / L[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {  // backward: L^T x = y
+            double s = col[i];
+            for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * col[k];
+            col[i] = s / L[(size_t)i * n + i];
+        }
+        for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = col[i];
+    }
+    A.swap(inv);
+    return true;
+}
+
+// Galerkin coarsening P^T K P of a 9-point operator on interior nodes, with
+// P the bilinear interpolation from the (nc-1)^2 coarse to the (2nc-1)^2 fine nodes.
+std::vector<double> rap(const std::vector<double>& Sf, int nf) {
+    const int nc = nf / 2, nxf = nf - 1, nxc = nc - 1;
+    std::vector<double> Sc((size_t)nxc * nxc * 9, 0.0);
+    auto wt = [](int d) { return d == 0 ? 1.0 : 0.5; };
+    for (int Y = 0; Y < nxc; ++Y)
+        for (int X = 0; X < nxc; ++X) {
+            double* out = &Sc[((size_t)Y * nxc + X) * 9];
+            for (int ay = -1; ay <= 1; ++ay)
+                for (int ax = -1; ax <= 1; ++ax) {
+                    const int fx = 2 * X + 1 + ax, fy = 2 * Y + 1 + ay;  // fine node a
+                    const double pa = wt(ax) * wt(ay);
+                    const double* st = &Sf[((size_t)fy * nxf + fx) * 9];
+                    for (int ey = -1; ey <= 1; ++ey)
+                        for (int ex = -1; ex <= 1; ++ex) {
+                            const int bx = fx + ex, by = fy + ey;  // fine node b
+                            if (bx < 0 || by < 0 || bx >= nxf || by >= nxf) continue;
+                            const double kab = st[(ey + 1) * 3 + (ex + 1)];
+                            if (kab == 0.0) continue;
+                            // coarse nodes J with P(b, J) != 0
+                            int jx[2], jy[2], cx = 0, cy = 0;
+                            double wx[2], wy[2];
+                            if (bx % 2 == 1) { jx[0] = (bx - 1) / 2; wx[0] = 1.0; cx = 1; }
+                            else { jx[0] = bx / 2 - 1; jx[1] = bx / 2; wx[0] = wx[1] = 0.5; cx = 2; }
+                            if (by % 2 == 1) { jy[0] = (by - 1) / 2; wy[0] = 1.0; cy = 1; }
+                            else { jy[0] = by / 2 - 1; jy[1] = by / 2; wy[0] = wy[1] = 0.5; cy = 2; }
+                            for (int iy = 0; iy < cy; ++iy)
+                                for (int ix = 0; ix < cx; ++ix) {
+                                    const int JX = jx[ix], JY = jy[iy];
+                                    if (JX < 0 || JY < 0 || JX >= nxc || JY >= nxc) continue;
+                                    const int ox = JX - X, oy = JY - Y;
+                                    out[(oy + 1) * 3 + (ox + 1)] += pa * kab * wx[ix] * wy[iy];
+                                }
+                        }
+                }
+        }
+    return Sc;
+}
+
+}  // namespace
+
+int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_amp, HostSetup& hs) {
+    const int n = opt.n_cells, m = opt.m, p = opt.p;
+    hs.n = n;
+    hs.m = m;
+    hs.p = p;
+    hs.N = (n - 1) * (n - 1);
+
+    // chaos index set and degree levels
+    auto idx = graded_indices(m, p);
+    hs.P = (int)idx.size();
+    hs.midx.assign((size_t)hs.P * m, 0);
+    hs.offsets.assign(p + 2, 0);
+    for (int a = 0; a < hs.P; ++a) {
+        int deg = 0;
+        for (int k = 0; k < m; ++k) {
+            hs.midx[(size_t)a * m + k] = idx[a][k];
+            deg += idx[a][k];
+        }
+        hs.offsets[deg + 1] = a + 1;
+    }
+    for (int d = 1; d <= p + 1; ++d) hs.offsets[d] = std::max(hs.offsets[d], hs.offsets[d - 1]);
+
+    // KL modes: products of 1-D modes, the m largest products, ties by (i, j)
+    hs.lambda.assign(m, 0.0);
+    hs.amps.assign(m, 0.0);
+    std::vector<Mode1D> m1;
+    std::vector<std::pair<int, int>> pick;
+    if (m > 0) {
+        m1 = kl_1d(opt.corr_len, m + 1);
+        struct Cand { double lam; int i, j; };
+        std::vector<Cand> cand;
+        for (int i = 0; i <= m; ++i)
+            for (int j = 0; j <= m; ++j) cand.push_back({m1[i].lam * m1[j].lam, i, j});
+        std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) {
+            if (x.lam != y.lam) return x.lam > y.lam;
+            if (x.i != y.i) return x.i < y.i;
+            return x.j < y.j;
+        });
+        for (int k = 0; k < m; ++k) {
+            pick.push_back({cand[k].i, cand[k].j});
+            hs.lambda[k] = cand[k].lam;
+            hs.amps[k] = kl_amp ? kl_amp[k] : std::sqrt(cand[k].lam);
+        }
+    }
+
+    // cell coefficients (midpoint rule per cell)
+    const double h = 1.0 / n;
+    const size_t ncell = (size_t)n * n;
+    hs.cellc.assign((size_t)(m + 1) * ncell, 0.0);
+    hs.klcell.assign((size_t)m * ncell, 0.0);
+    for (int cy = 0; cy < n; ++cy)
+        for (int cx = 0; cx < n; ++cx) {
+            const size_t e = (size_t)cy * n + cx;
+            double a0 = 1.0;
+            if (a0_nodal) {
+                const size_t v = (size_t)cy * (n + 1) + cx;
+                a0 = 0.25 * (a0_nodal[v] + a0_nodal[v + 1] + a0_nodal[v + n + 1] + a0_nodal[v + n + 2]);
+            }
+            hs.cellc[e] = a0;
+            const double t1 = (cx + 0.5) * h - 0.5, t2 = (cy + 0.5) * h - 0.5;
+            double spread = 0.0;
+            for (int k = 0; k < m; ++k) {
+                const double b = eval1d(m1[pick[k].first], t1) * eval1d(m1[pick[k].second], t2);
+                hs.klcell[(size_t)k * ncell + e] = b;
+                const double ck = opt.sigma * hs.amps[k] * b;
+                hs.cellc[(size_t)(k + 1) * ncell + e] = ck;
+                spread += std::fabs(ck);
+            }
+            const double margin = a0 - spread;
+            if (e == 0 || margin < hs.a_min_h) hs.a_min_h = margin;
+        }
+
+    // fine K_0 stencil from the cell means: node (x, y) touches cells
+    // SW (x, y), SE (x+1, y), NW (x, y+1), NE (x+1, y+1); element matrix
+    // entries 4/6 (own vertex), -1/6 (edge neighbour), -2/6 (opposite vertex).
+    hs.mg_n.clear();
+    hs.mg_sten.clear();
+    {
+        const int nx = n - 1;
+        std::vector<double> st((size_t)nx * nx * 9, 0.0);
+        for (int y = 0; y < nx; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const double sw = hs.cellc[(size_t)y * n + x], se = hs.cellc[(size_t)y * n + x + 1];
+                const double nw = hs.cellc[(size_t)(y + 1) * n + x], ne = hs.cellc[(size_t)(y + 1) * n + x + 1];
+                double* s = &st[((size_t)y * nx + x) * 9];
+                s[0] = -2.0 * sw / 6.0;          // (-1,-1)
+                s[1] = -(sw + se) / 6.0;         // ( 0,-1)
+                s[2] = -2.0 * se / 6.0;          // (+1,-1)
+                s[3] = -(sw + nw) / 6.0;         // (-1, 0)
+                s[4] = 4.0 * (sw + se + nw + ne) / 6.0;
+                s[5] = -(se + ne) / 6.0;         // (+1, 0)
+                s[6] = -2.0 * nw / 6.0;          // (-1,+1)
+                s[7] = -(nw + ne) / 6.0;         // ( 0,+1)
+                s[8] = -2.0 * ne / 6.0;          // (+1,+1)
+            }
+        hs.mg_n.push_back(n);
+        hs.mg_sten.push_back(std::move(st));
+    }
+    while (hs.mg_n.back() > opt.coarsest_cells) {
+        const int nf = hs.mg_n.back();
+        hs.mg_sten.push_back(rap(hs.mg_sten.back(), nf));
+        hs.mg_n.push_back(nf / 2);
+    }
+    {
+        const int nc = hs.mg_n.back(), nxc = nc - 1, Nc = nxc * nxc;
+        const auto& st = hs.mg_sten.back();
+        std::vector<double> A((size_t)Nc * Nc, 0.0);
+        for (int y = 0; y < nxc; ++y)
+            for (int x = 0; x < nxc; ++x)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int X = x + dx, Y = y + dy;
+                        if (X < 0 || Y < 0 || X >= nxc || Y >= nxc) continue;
+                        A[(size_t)(y * nxc + x) * Nc + (Y * nxc + X)] = st[((size_t)y * nxc + x) * 9 + (dy + 1) * 3 + (dx + 1)];
+                    }
+        if (!cholesky_inverse(A, Nc)) {
+            set_error("coarsest-grid operator is not positive definite");
+            return SG_EINVAL;
+        }
+        hs.coarse_inv.swap(A);
+    }
+    return hs.a_min_h > 0.0 ? SG_OK : SG_WNOTCOERCIVE;
+}
+
+PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_out, bool self, bool up, bool down) {
+    PlanHost pl;
+    pl.in_lo = in_lo;
+    pl.W_in = W_in;
+    pl.out_lo = out_lo;
+    pl.W_out = W_out;
+    pl.self = self ? 1 : 0;
+    pl.nslot = std::max((W_in + 63) / 64, (W_out + 63) / 64);
+    if (pl.nslot < 1) pl.nslot = 1;
+    const int m = hs.m, lanes = pl.nslot * 64;
+    const uint32_t zero = (uint32_t)(m * lanes);
+    pl.off.assign((size_t)lanes * std::max(m, 1), zero | (zero << 16));
+    pl.coef.assign((size_t)lanes * std::max(m, 1) * 2, 0.0);
+    std::map<std::vector<int>, int> pos;
+    for (int a = 0; a < hs.P; ++a)
+        pos[std::vector<int>(hs.midx.begin() + (size_t)a * m, hs.midx.begin() + (size_t)(a + 1) * m)] = a;
+    for (int t = 0; t < W_out; ++t) {
+        const int a = out_lo + t;
+        std::vector<int> al(hs.midx.begin() + (size_t)a * m, hs.midx.begin() + (size_t)(a + 1) * m);
+        for (int k = 0; k < m; ++k) {
+            uint32_t iu = zero, id = zero;
+            double cu = 0.0, cd = 0.0;
+            if (up) {
+                auto b = al;
+                b[k] += 1;
+                auto it = pos.find(b);
+                if (it != pos.end() && it->second >= in_lo && it->second < in_lo + W_in) {
+                    iu = (uint32_t)(k * lanes + (it->second - in_lo));
+                    cu = legendre_b(al[k] + 1);
+                }
+            }
+            if (down && al[k] > 0) {
+                auto b = al;
+                b[k] -= 1;
+                auto it = pos.find(b);
+                if (it != pos.end() && it->second >= in_lo && it->second < in_lo + W_in) {
+                    id = (uint32_t)(k * lanes + (it->second - in_lo));
+                    cd = legendre_b(al[k]);
+                }
+            }
+            pl.off[(size_t)t * m + k] = iu | (id << 16);
+            pl.coef[((size_t)t * m + k) * 2 + 0] = cu;
+            pl.coef[((size_t)t * m + k) * 2 + 1] = cd;
+        }
+    }
+    return pl;
+}
+
+}  // namespace sg

@@ -1,0 +1,35 @@
+// Launchers of the vector, reduction, QoI and adjoint kernels (sg_vec.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+
+namespace sg {
+
+constexpr int kRedBlocks = 1024;  // fixed reduction grid: deterministic partial sums
+
+hipError_t vec_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* w, size_t len,
+                        double* partial, double* out);
+hipError_t vec_update(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w, size_t len,
+                      double* partial_sq, double* out_sq);
+hipError_t vec_dot(hipStream_t s, const double* a, const double* b, size_t len, double* partial, double* out);
+hipError_t vec_scale(hipStream_t s, const double* src, double a, double* dst, size_t len);
+hipError_t vec_combine(hipStream_t s, const void* Z, int z_float, size_t stride, int nz, const double* y, double* x,
+                       size_t len);
+hipError_t vec_axpy_sq(hipStream_t s, double a, const double* x, double* y, size_t len, double* partial,
+                       double* out_sq);
+hipError_t vec_axpy(hipStream_t s, double a, const double* x, double* y, size_t len);
+hipError_t vec_xpby(hipStream_t s, const double* z, double b, double* p, size_t len);
+hipError_t vec_rhs(hipStream_t s, double* F, int N, int P, double h2);
+hipError_t vec_qoi(hipStream_t s, const double* U, const double* wS, int N, int P, double* partial, double* q,
+                   double* J, double* coef);
+hipError_t vec_adj_rhs(hipStream_t s, const double* wS, const double* coef, int N, int P, double* g);
+hipError_t vec_grad_cells(hipStream_t s, int nslot, const double* U, const double* L, int n, int P, int m,
+                          const uint32_t* toff, const double* tcoef, double* dc);
+hipError_t vec_grad_params(hipStream_t s, const double* dc, const double* kl, const double* amps, double sigma, int n,
+                           int m, double* partial, double* Tk, double* out_params, double* out_a0);
+
+}  // namespace sg

@@ -1,0 +1,417 @@
+// Krylov vector kernels, QoI reductions and the adjoint cell gradient.
+//
+// Reductions are deterministic: a fixed grid of kRedBlocks blocks walks the
+// vector with a grid stride, each block reduces in a fixed tree (wavefront
+// shuffles, then LDS across its 4 waves) and writes one partial per output;
+// a second one-block kernel sums the partials in a fixed order.  No float
+// atomics, so repeated runs are bitwise identical.
+
+#include "sg_internal.h"
+#include "sg_vec.h"
+
+namespace sg {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// block of 256 threads: returns the block sum in every thread of wave 0 lane 0
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    return t;
+}
+
+// partial[b][i] = sum over block b's elements of V_i[e] * w[e], i < nv (nv <= 16)
+__global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, size_t stride, int nv,
+                                                  const double* __restrict__ w, size_t len,
+                                                  double* __restrict__ partial) {
+    __shared__ double sh[4];
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
+        const double we = w[e];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < nv) acc[i] = fma(V[(size_t)i * stride + e], we, acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i < nv) {  // uniform: keeps the loop unrolled and acc[] in registers
+            const double t = block_sum(acc[i], sh);
+            if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 16 + i] = t;
+        }
+    }
+}
+
+// out[i] = sum_b partial[b][i], fixed order
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nblocks, int width, int ldp,
+                                  double* __restrict__ out) {
+    __shared__ double sh[4];
+    for (int i = 0; i < width; ++i) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[(size_t)b * ldp + i];
+        const double t = block_sum(v, sh);
+        if (threadIdx.x == 0) out[i] = t;
+    }
+}
+
+// w -= sum_i h[i] V_i ; optionally partial sums of the new w^2
+__global__ void __launch_bounds__(256) k_update(const double* __restrict__ V, size_t stride, int nv,
+                                                const double* __restrict__ h, double* __restrict__ w, size_t len,
+                                                double* __restrict__ partial_sq) {
+    __shared__ double sh[4];
+    __shared__ double hs[16];
+    if (threadIdx.x < 16) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
+    __syncthreads();
+    double sq = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
+        double we = w[e];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < nv) we = fma(-hs[i], V[(size_t)i * stride + e], we);
+        w[e] = we;
+        sq = fma(we, we, sq);
+    }
+    if (partial_sq) {
+        const double t = block_sum(sq, sh);
+        if (threadIdx.x == 0) partial_sq[blockIdx.x] = t;
+    }
+}
+
+__global__ void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b, size_t len,
+                              double* __restrict__ partial) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+        acc = fma(a[e], b[e], acc);
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void k_scale(const double* __restrict__ src, double a, double* __restrict__ dst, size_t len) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+        dst[e] = a * src[e];
+}
+
+// x += sum_i y[i] Z_i  (Z float or double)
+template <typename TZ>
+__global__ void k_combine(const TZ* __restrict__ Z, size_t stride, int nz, const double* __restrict__ y,
+                          double* __restrict__ x, size_t len) {
+    __shared__ double ys[kMaxRestart];
+    for (int i = threadIdx.x; i < nz; i += blockDim.x) ys[i] = y[i];
+    __syncthreads();
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
+        double acc = x[e];
+        for (int i = 0; i < nz; ++i) acc = fma(ys[i], (double)Z[(size_t)i * stride + e], acc);
+        x[e] = acc;
+    }
+}
+
+// y = a*x + y  and partial sums of y^2 (PCG residual update)
+__global__ void k_axpy_sq(double a, const double* __restrict__ x, double* __restrict__ y, size_t len,
+                          double* __restrict__ partial_sq) {
+    __shared__ double sh[4];
+    double sq = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
+        const double v = fma(a, x[e], y[e]);
+        y[e] = v;
+        sq = fma(v, v, sq);
+    }
+    const double t = block_sum(sq, sh);
+    if (threadIdx.x == 0) partial_sq[blockIdx.x] = t;
+}
+
+__global__ void k_axpy(double a, const double* __restrict__ x, double* __restrict__ y, size_t len) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+        y[e] = fma(a, x[e], y[e]);
+}
+
+// p = z + b p
+__global__ void k_xpby(const double* __restrict__ z, double b, double* __restrict__ p, size_t len) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+        p[e] = fma(b, p[e], z[e]);
+}
+
+// F = e_0 (x) f_h with f_h,i = h^2 (f = 1)
+__global__ void k_rhs(double* __restrict__ F, int N, int P, double h2) {
+    const size_t len = (size_t)N * P;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+        F[e] = (e % P) == 0 ? h2 : 0.0;
+}
+
+// q partials: partial[b][a] = sum over node rows of block b of w_S[i] U[i][a]
+__global__ void k_qoi_partial(const double* __restrict__ U, const double* __restrict__ wS, int N, int P,
+                              double* __restrict__ partial, int ldp) {
+    // threads cover modes (strided by blockDim.x); each block walks its node range
+    const int per = (N + gridDim.x - 1) / gridDim.x;
+    const int i0 = blockIdx.x * per, i1 = min(N, i0 + per);
+    for (int a = threadIdx.x; a < P; a += blockDim.x) {
+        double acc = 0.0;
+        for (int i = i0; i < i1; ++i) acc = fma(wS[i], U[(size_t)i * P + a], acc);
+        partial[(size_t)blockIdx.x * ldp + a] = acc;
+    }
+}
+
+// J = q_0 + sum_{a>0} q_a^2 and the adjoint weights coef_a = (a == 0 ? 1 : 2 q_a)
+__global__ void k_qoi_finish(const double* __restrict__ q, int P, double* __restrict__ J, double* __restrict__ coef) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int a = 1; a < P; ++a) s = fma(q[a], q[a], s);
+        *J = q[0] + s;
+    }
+    for (int a = threadIdx.x; a < P; a += blockDim.x) coef[a] = a == 0 ? 1.0 : 2.0 * q[a];
+}
+
+__global__ void k_adj_rhs(const double* __restrict__ wS, const double* __restrict__ coef, int N, int P,
+                          double* __restrict__ g) {
+    const size_t len = (size_t)N * P;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = e / P;
+        g[e] = wS[i] * coef[e - i * P];
+    }
+}
+
+// dc[e][k] = -sum_{a,b} G_k(a,b) lam_{a,e}^T K_ref U_{b,e}.  One wave per cell,
+// lanes over modes; the element action t = K_ref U_b (times 6) is shared with
+// the coupling partners through LDS.  toff/tcoef: the full coupling plan
+// (packed LDS slots k*lanes + b of alpha +- e_k, coefficients G_k).
+template <int NS>
+__global__ void __launch_bounds__(256) k_grad_cells(const double* __restrict__ U, const double* __restrict__ L,
+                                                    int n, int P, int m, const uint32_t* __restrict__ toff,
+                                                    const double* __restrict__ tcoef, double* __restrict__ dc) {
+    constexpr int LANES = NS * 64;
+    extern __shared__ double lds_raw[];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double* T = lds_raw + wv * (4 * LANES + 2);
+    const int cellid = blockIdx.x * 4 + wv;
+    if (cellid >= n * n) return;
+    const int cy = cellid / n, cx = cellid - cy * n;
+    const int nx = n - 1;
+    // vertices CCW from the lower-left: grid (cx,cy), (cx+1,cy), (cx+1,cy+1), (cx,cy+1)
+    const int vx[4] = {cx, cx + 1, cx + 1, cx};
+    const int vy[4] = {cy, cy, cy + 1, cy + 1};
+    double u[NS][4], l[NS][4], t[NS][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const bool inside = vx[v] >= 1 && vx[v] <= nx && vy[v] >= 1 && vy[v] <= nx;
+        const size_t node = inside ? (size_t)(vy[v] - 1) * nx + (vx[v] - 1) : 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int a = s * 64 + lane;
+            const bool ok = inside && a < P;
+            u[s][v] = ok ? U[node * P + a] : 0.0;
+            l[s][v] = ok ? L[node * P + a] : 0.0;
+        }
+    }
+    double acc[kMaxM + 1];
+#pragma unroll
+    for (int k = 0; k <= kMaxM; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        // 6 K_ref u: 4 u_v - u_(v+1) - u_(v+3) - 2 u_(v+2)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            t[s][v] = 4.0 * u[s][v] - u[s][(v + 1) & 3] - u[s][(v + 3) & 3] - 2.0 * u[s][(v + 2) & 3];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            acc[0] = fma(l[s][v], t[s][v], acc[0]);
+            T[v * LANES + s * 64 + lane] = t[s][v];
+        }
+    }
+    if (lane == 0) T[4 * LANES] = 0.0;
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __asm__ __volatile__("" ::: "memory");
+    const uint32_t zero = (uint32_t)(m * LANES);
+    for (int k = 0; k < m; ++k) {
+        double ak = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int a = s * 64 + lane;
+            if (a >= P) continue;
+            const size_t ti = (size_t)a * m + k;
+            const uint32_t o = toff[ti];
+            const uint32_t iu = o & 0xFFFFu, id = o >> 16;
+            const double cu = tcoef[2 * ti], cd = tcoef[2 * ti + 1];
+            if (iu != zero) {
+                const int b = (int)iu - k * LANES;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ak = fma(cu * l[s][v], T[v * LANES + b], ak);
+            }
+            if (id != zero) {
+                const int b = (int)id - k * LANES;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ak = fma(cd * l[s][v], T[v * LANES + b], ak);
+            }
+        }
+#pragma unroll
+        for (int kk = 1; kk <= kMaxM; ++kk)
+            if (kk == k + 1) acc[kk] = ak;
+    }
+#pragma unroll
+    for (int k = 0; k <= kMaxM; ++k) {
+        if (k <= m) {
+            const double s = wave_sum(acc[k]);
+            if (lane == 0) dc[(size_t)cellid * (m + 1) + k] = -s / 6.0;
+        }
+    }
+}
+
+// partial[b][k] = sum over cells of block b of dc[e][k+1] * b_k(e), k < m
+__global__ void k_grad_kl_partial(const double* __restrict__ dc, const double* __restrict__ kl, int ncell, int m,
+                                  double* __restrict__ partial) {
+    __shared__ double sh[4];
+    for (int k = 0; k < m; ++k) {
+        double acc = 0.0;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ncell; e += gridDim.x * blockDim.x)
+            acc = fma(dc[(size_t)e * (m + 1) + k + 1], kl[(size_t)e * m + k], acc);
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 16 + k] = t;
+    }
+}
+
+// out[0] = dJ/dsigma = sum_k s_k T_k, out[1+k] = dJ/ds_k = sigma T_k
+__global__ void k_grad_kl_finish(const double* __restrict__ Tk, const double* __restrict__ amps, double sigma, int m,
+                                 double* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s = fma(amps[k], Tk[k], s);
+        out[0] = s;
+        for (int k = 0; k < m; ++k) out[1 + k] = sigma * Tk[k];
+    }
+}
+
+// dJ/da0 at interior node (x, y): a quarter of dJ/dc_0 of its four cells
+__global__ void k_grad_a0(const double* __restrict__ dc, int n, int m, double* __restrict__ out) {
+    const int nx = n - 1;
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= nx * nx) return;
+    const int y = node / nx, x = node - y * nx;
+    const int s = m + 1;
+    const double v = dc[((size_t)y * n + x) * s] + dc[((size_t)y * n + x + 1) * s] +
+                     dc[((size_t)(y + 1) * n + x) * s] + dc[((size_t)(y + 1) * n + x + 1) * s];
+    out[node] = 0.25 * v;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t vec_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* w, size_t len,
+                        double* partial, double* out) {
+    // nv may exceed 16: process the basis in chunks
+    for (int c0 = 0; c0 < nv; c0 += 16) {
+        const int cn = std::min(16, nv - c0);
+        hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(256), 0, s, V + (size_t)c0 * stride, stride, cn, w, len,
+                           partial);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, cn, 16, out + c0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t vec_update(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w, size_t len,
+                      double* partial_sq, double* out_sq) {
+    for (int c0 = 0; c0 < nv; c0 += 16) {
+        const int cn = std::min(16, nv - c0);
+        const bool last = c0 + 16 >= nv;
+        hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, s, V + (size_t)c0 * stride, stride, cn, h + c0, w,
+                           len, (last && partial_sq) ? partial_sq : nullptr);
+    }
+    if (partial_sq && out_sq)
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial_sq, kRedBlocks, 1, 1, out_sq);
+    return hipGetLastError();
+}
+
+hipError_t vec_dot(hipStream_t s, const double* a, const double* b, size_t len, double* partial, double* out) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, len, partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, 1, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t vec_scale(hipStream_t s, const double* src, double a, double* dst, size_t len) {
+    hipLaunchKernelGGL(k_scale, dim3(kRedBlocks), dim3(256), 0, s, src, a, dst, len);
+    return hipGetLastError();
+}
+
+hipError_t vec_combine(hipStream_t s, const void* Z, int z_float, size_t stride, int nz, const double* y, double* x,
+                       size_t len) {
+    if (z_float)
+        hipLaunchKernelGGL(k_combine<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)Z, stride, nz, y, x, len);
+    else
+        hipLaunchKernelGGL(k_combine<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)Z, stride, nz, y, x,
+                           len);
+    return hipGetLastError();
+}
+
+hipError_t vec_axpy_sq(hipStream_t s, double a, const double* x, double* y, size_t len, double* partial,
+                       double* out_sq) {
+    hipLaunchKernelGGL(k_axpy_sq, dim3(kRedBlocks), dim3(256), 0, s, a, x, y, len, partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, 1, 1, out_sq);
+    return hipGetLastError();
+}
+
+hipError_t vec_axpy(hipStream_t s, double a, const double* x, double* y, size_t len) {
+    hipLaunchKernelGGL(k_axpy, dim3(kRedBlocks), dim3(256), 0, s, a, x, y, len);
+    return hipGetLastError();
+}
+
+hipError_t vec_xpby(hipStream_t s, const double* z, double b, double* p, size_t len) {
+    hipLaunchKernelGGL(k_xpby, dim3(kRedBlocks), dim3(256), 0, s, z, b, p, len);
+    return hipGetLastError();
+}
+
+hipError_t vec_rhs(hipStream_t s, double* F, int N, int P, double h2) {
+    hipLaunchKernelGGL(k_rhs, dim3(kRedBlocks), dim3(256), 0, s, F, N, P, h2);
+    return hipGetLastError();
+}
+
+hipError_t vec_qoi(hipStream_t s, const double* U, const double* wS, int N, int P, double* partial, double* q,
+                   double* J, double* coef) {
+    hipLaunchKernelGGL(k_qoi_partial, dim3(kRedBlocks), dim3(256), 0, s, U, wS, N, P, partial, P);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, P, P, q);
+    hipLaunchKernelGGL(k_qoi_finish, dim3(1), dim3(256), 0, s, q, P, J, coef);
+    return hipGetLastError();
+}
+
+hipError_t vec_adj_rhs(hipStream_t s, const double* wS, const double* coef, int N, int P, double* g) {
+    hipLaunchKernelGGL(k_adj_rhs, dim3(kRedBlocks), dim3(256), 0, s, wS, coef, N, P, g);
+    return hipGetLastError();
+}
+
+hipError_t vec_grad_cells(hipStream_t s, int nslot, const double* U, const double* L, int n, int P, int m,
+                          const uint32_t* toff, const double* tcoef, double* dc) {
+    const int blocks = (n * n + 3) / 4;
+    const size_t shm = (size_t)4 * (4 * nslot * 64 + 2) * sizeof(double);
+    switch (nslot) {
+        case 1: hipLaunchKernelGGL(k_grad_cells<1>, dim3(blocks), dim3(256), shm, s, U, L, n, P, m, toff, tcoef, dc); break;
+        case 2: hipLaunchKernelGGL(k_grad_cells<2>, dim3(blocks), dim3(256), shm, s, U, L, n, P, m, toff, tcoef, dc); break;
+        case 3: hipLaunchKernelGGL(k_grad_cells<3>, dim3(blocks), dim3(256), shm, s, U, L, n, P, m, toff, tcoef, dc); break;
+        case 4: hipLaunchKernelGGL(k_grad_cells<4>, dim3(blocks), dim3(256), shm, s, U, L, n, P, m, toff, tcoef, dc); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t vec_grad_params(hipStream_t s, const double* dc, const double* kl, const double* amps, double sigma, int n,
+                           int m, double* partial, double* Tk, double* out_params, double* out_a0) {
+    if (m > 0) {
+        hipLaunchKernelGGL(k_grad_kl_partial, dim3(kRedBlocks), dim3(256), 0, s, dc, kl, n * n, m, partial);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, m, 16, Tk);
+    }
+    hipLaunchKernelGGL(k_grad_kl_finish, dim3(1), dim3(64), 0, s, Tk, amps, sigma, m, out_params);
+    const int nn = (n - 1) * (n - 1);
+    hipLaunchKernelGGL(k_grad_a0, dim3((nn + 255) / 256), dim3(256), 0, s, dc, n, m, out_a0);
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -1,0 +1,86 @@
+"""GPU adjoint gradient of J = E[Q] + Var[Q] against the oracle and central differences."""
+
+import numpy as np
+import pytest
+import torch
+
+import sg_inputs
+from gpu_util import note, to_host
+from oracle import qoi, system
+
+pytestmark = pytest.mark.gpu
+
+SOLVE = dict(precond="tri", prec=0, restart=40, rtol=1e-13, max_it=400)
+
+
+def test_gradient_matches_oracle_small():
+    import paper_1304_1755_amd as sgbt
+    note("adjoint small vs oracle")
+    n, m, p, sigma = 16, 2, 2, 0.3
+    a0 = sg_inputs.a0_noise_field(n)
+    g = sgbt.Problem(n, m, p, sigma, a0_nodal=a0)
+    o = system.build_problem(n, m, p, sigma, a0_nodal=a0)
+    ref = qoi.qoi_and_gradient(o)
+    U, info = g.solve(**SOLVE)
+    J, q = g.qoi(U)
+    assert abs(J - ref["J"]) < 1e-11 * abs(ref["J"])
+    gr = g.qoi_grad(U, **SOLVE)
+    assert abs(gr["dsigma"] - ref["dsigma"]) < 1e-8 * max(1, abs(ref["dsigma"]))
+    assert np.max(np.abs(gr["damp"] - ref["damp"])) < 1e-8 * max(1, np.max(np.abs(ref["damp"])))
+    assert np.max(np.abs(gr["da0"] - ref["da0"])) < 1e-8 * np.max(np.abs(ref["da0"]))
+    g.close()
+
+
+def _J(cfg, sigma, amps, a0):
+    import paper_1304_1755_amd as sgbt
+    g = sgbt.Problem(cfg["n"], cfg["m"], cfg["p"], sigma, cfg["corr_len"], a0_nodal=a0, kl_amp=amps)
+    U, info = g.solve(**SOLVE)
+    J, _ = g.qoi(U)
+    g.close()
+    return J
+
+
+def test_gradient_against_central_differences_c5():
+    import paper_1304_1755_amd as sgbt
+    note("adjoint c5 finite differences")
+    cfg = sg_inputs.CONFIGS["c5"]
+    n, m = cfg["n"], cfg["m"]
+    a0 = sg_inputs.a0_noise_field(n)
+    g = sgbt.Problem(n, m, cfg["p"], cfg["sigma"], cfg["corr_len"], a0_nodal=a0)
+    amps = np.sqrt(np.array(g.kl_lambda))
+    U, info = g.solve(**SOLVE)
+    assert info["rel_res_true"] < 1e-12
+    gr = g.qoi_grad(U, **SOLVE)
+    g.close()
+    grad = np.concatenate([[gr["dsigma"]], gr["damp"], gr["da0"]])
+    dirs = sg_inputs.unit_directions(20, grad.size, seed=7)
+    h = 1e-6
+    inner = np.zeros((n + 1, n + 1))
+    for t, v in enumerate(dirs):
+        note(f"fd direction {t}")
+        inner[1:n, 1:n] = v[1 + m:].reshape(n - 1, n - 1)
+        va0 = inner.ravel().copy()
+        Jp = _J(cfg, cfg["sigma"] + h * v[0], amps + h * v[1:1 + m], a0 + h * va0)
+        Jm = _J(cfg, cfg["sigma"] - h * v[0], amps - h * v[1:1 + m], a0 - h * va0)
+        fd = (Jp - Jm) / (2 * h)
+        ad = float(grad @ v)
+        # per direction: |grad.v - FD| / max(|FD|, 1e-3 ||grad|| ||v||) <= 1e-6
+        assert abs(ad - fd) / max(abs(fd), 1e-3 * np.linalg.norm(grad)) <= 1e-6, (t, ad, fd)
+
+
+def test_autograd_function():
+    import paper_1304_1755_amd as sgbt
+    note("autograd function")
+    n, m, p = 16, 2, 2
+    o = system.build_problem(n, m, p, 0.3)
+    sigma = torch.tensor(0.3, dtype=torch.float64, requires_grad=True)
+    amps = torch.tensor(o.kldata["amps"], dtype=torch.float64, requires_grad=True)
+    a0 = torch.ones((n + 1) ** 2, dtype=torch.float64, requires_grad=True)
+    J = sgbt.SGQoI.apply(sigma, amps, a0, dict(n=n, m=m, p=p, solve=SOLVE))
+    J.backward()
+    ref = qoi.qoi_and_gradient(o)
+    assert abs(J.item() - ref["J"]) < 1e-11 * abs(ref["J"])
+    assert abs(sigma.grad.item() - ref["dsigma"]) < 1e-8 * max(1, abs(ref["dsigma"]))
+    ga0 = a0.grad.reshape(n + 1, n + 1)[1:n, 1:n].reshape(-1).numpy()
+    assert np.max(np.abs(ga0 - ref["da0"])) < 1e-8 * np.max(np.abs(ref["da0"]))
+    assert torch.all(a0.grad.reshape(n + 1, n + 1)[0] == 0)

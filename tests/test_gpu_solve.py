@@ -1,0 +1,112 @@
+"""GPU Krylov solves against the oracle: solution, true residual and iteration counts.
+
+Bar: true relative residual < 1e-8 (double, recomputed on the host side from
+the oracle's matrix), solution within 1e-6 relative of the oracle's direct
+solution, iteration counts within +-1 of the oracle running the same
+algorithm (same preconditioner, same colour order).
+"""
+
+import numpy as np
+import pytest
+
+import sg_inputs
+from gpu_util import note, rel_max, to_dev, to_host
+from oracle import krylov, mg, precond, system
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_solve(o, kind, inner, solver="fgmres", restart=30, tol=1e-8):
+    A = system.assemble_A(o)
+    fn = precond.precond_tri if kind == "tri" else precond.precond_diag
+    M = lambda v: fn(o, v.reshape(o.P, o.N), inner).ravel()  # noqa: E731
+    F = o.rhs().ravel()
+    if solver == "fgmres":
+        x, info = krylov.fgmres(lambda v: A @ v, F, M, restart=restart, tol=tol)
+    else:
+        x, info = krylov.pcg(lambda v: A @ v, F, M, tol=tol)
+    return A, x.reshape(o.P, o.N), info
+
+
+def test_c1_exact_k0_blocks():
+    import paper_1304_1755_amd as sgbt
+    note("solve c1 fgmres tri exact")
+    c = sg_inputs.CONFIGS["c1"]
+    g = sgbt.Problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"], coarsest=c["n"])
+    o = system.build_problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"])
+    A, xo, io = _oracle_solve(o, "tri", precond.ExactK0(o.K[0]))
+    U, info = g.solve(precond="tri", restart=30, rtol=1e-8)
+    Uh = to_host(U)
+    Ustar = system.solve_direct(o, A=A)
+    F = o.rhs().ravel()
+    assert np.linalg.norm(F - A @ Uh.T.ravel()) / np.linalg.norm(F) < 1e-8
+    assert rel_max(Uh.T, Ustar) < 1e-6
+    assert abs(info["iters"] - io["iters"]) <= 1
+    g.close()
+
+
+@pytest.mark.parametrize("sigma", [0.1, 0.3, 0.5])
+def test_c2_bt_gmres_and_bd_pcg(sigma):
+    import paper_1304_1755_amd as sgbt
+    note(f"solve c2 sigma={sigma}")
+    c = sg_inputs.CONFIGS["c2"]
+    g = sgbt.Problem(c["n"], c["m"], c["p"], sigma, c["corr_len"], colour="rb", nu1=1, nu2=1)
+    o = system.build_problem(c["n"], c["m"], c["p"], sigma, c["corr_len"])
+    H = mg.Hierarchy(o.K[0], c["n"], coarsest=8, colour_mode="rb", nu1=1, nu2=1)
+    A, _, io_t = _oracle_solve(o, "tri", H.vcycle)
+    _, _, io_d = _oracle_solve(o, "diag", H.vcycle, solver="pcg")
+    Ustar = system.solve_direct(o, A=A)
+    F = o.rhs().ravel()
+    for kind, solver, io in (("tri", "fgmres", io_t), ("diag", "pcg", io_d)):
+        note(f"solve c2 sigma={sigma} {kind} {solver}")
+        U, info = g.solve(solver=solver, precond=kind, restart=30, rtol=1e-8)
+        Uh = to_host(U).T
+        assert np.linalg.norm(F - A @ Uh.ravel()) / np.linalg.norm(F) < 1e-8
+        assert rel_max(Uh, Ustar) < 1e-6
+        assert abs(info["iters"] - io["iters"]) <= 1, (info["iters"], io["iters"])
+    g.close()
+
+
+def test_c3_copy_mixed_precision():
+    import paper_1304_1755_amd as sgbt
+    note("solve c3_65 mixed")
+    c = sg_inputs.CONFIGS["c3_65"]
+    g = sgbt.Problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"])
+    o = system.build_problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"])
+    A = system.assemble_A(o)
+    Ustar = system.solve_direct(o, A=A)
+    F = o.rhs().ravel()
+    for prec in (0, 2):
+        note(f"solve c3_65 prec={prec}")
+        U, info = g.solve(precond="tri", prec=prec, restart=30, rtol=1e-8)
+        Uh = to_host(U).T
+        assert info["status"] == 0
+        assert np.linalg.norm(F - A @ Uh.ravel()) / np.linalg.norm(F) < 1e-8
+        assert rel_max(Uh, Ustar) < 1e-6
+    g.close()
+
+
+def test_restarts_initial_guess_and_errors():
+    import paper_1304_1755_amd as sgbt
+    note("solve restart/x0/errors")
+    g = sgbt.Problem(32, 3, 3, 0.4)
+    o = system.build_problem(32, 3, 3, 0.4)
+    A = system.assemble_A(o)
+    F = o.rhs().ravel()
+    U, info = g.solve(precond="tri", restart=2, rtol=1e-9, max_it=200)
+    assert info["restarts"] >= 1 and info["rel_res_true"] < 1e-9
+    Uh = to_host(U).T
+    assert np.linalg.norm(F - A @ Uh.ravel()) / np.linalg.norm(F) < 1e-9
+    # warm start from the solution: converges at once
+    U2, info2 = g.solve(U=U.clone(), use_x0=True, precond="tri", rtol=1e-8)
+    assert info2["iters"] == 0
+    # too few iterations: status ENOTCONV, the iterate is still returned
+    U3, info3 = g.solve(precond="diag", rtol=1e-12, max_it=2)
+    assert info3["status"] == sgbt.SG_ENOTCONV and info3["iters"] == 2
+    # NaN in the right-hand side
+    Fn = g.rhs()
+    Fn[3, 0] = float("nan")
+    with pytest.raises(sgbt.SGError) as e:
+        g.solve(F=Fn, precond="tri")
+    assert e.value.code == sgbt.SG_ENAN
+    g.close()
