@@ -86,15 +86,28 @@ def apply(prob, U):
     return Y
 
 
-def solve_direct(prob, F=None, A=None):
-    """Exact Galerkin solution U* of A vec(U) = vec(F), returned as (P, N)."""
+def solve_direct(prob, F=None, A=None, rtol=1e-14):
+    """Galerkin solution U* of A vec(U) = vec(F), returned as (P, N).
+
+    Dense LU up to 6000 unknowns, sparse LU up to 60000; larger systems use
+    conjugate gradients (A is SPD, Sec. 3) preconditioned by exact K_0 solves
+    on every mode, run to a relative residual of `rtol`, close to rounding.
+    """
     if F is None:
         F = prob.rhs()
     if A is None:
         A = assemble_A(prob)
     b = np.asarray(F, dtype=np.float64).reshape(-1)
-    if A.shape[0] <= 6000:
+    n = A.shape[0]
+    if n <= 6000:
         x = sla.solve(A.toarray(), b, assume_a="sym")
-    else:
+    elif n <= 60000:
         x = spla.spsolve(A.tocsc(), b)
+    else:
+        lu = spla.splu(prob.K[0].tocsc())
+        M = spla.LinearOperator((n, n), matvec=lambda v: lu.solve(
+            np.ascontiguousarray(v.reshape(prob.P, prob.N).T)).T.ravel())
+        x, info = spla.cg(A, b, rtol=rtol, atol=0.0, M=M, maxiter=2000)
+        if info != 0:
+            raise RuntimeError(f"reference CG did not reach {rtol}: info={info}")
     return x.reshape(prob.P, prob.N)

@@ -49,15 +49,17 @@ def test_gradient_against_central_differences_c5():
     g = sgbt.Problem(n, m, cfg["p"], cfg["sigma"], cfg["corr_len"], a0_nodal=a0)
     amps = np.sqrt(np.array(g.kl_lambda))
     U, info = g.solve(**SOLVE)
+    note(f"c5 forward solve: {info['iters']} it, status {info['status']}, residual {info['rel_res_true']:.2e}")
     assert info["rel_res_true"] < 1e-12
     gr = g.qoi_grad(U, **SOLVE)
+    note(f"c5 adjoint solve: {gr['adj_info']['iters']} it, residual {gr['adj_info']['rel_res_true']:.2e}")
     g.close()
     grad = np.concatenate([[gr["dsigma"]], gr["damp"], gr["da0"]])
     dirs = sg_inputs.unit_directions(20, grad.size, seed=7)
     h = 1e-6
     inner = np.zeros((n + 1, n + 1))
+    worst = 0.0
     for t, v in enumerate(dirs):
-        note(f"fd direction {t}")
         inner[1:n, 1:n] = v[1 + m:].reshape(n - 1, n - 1)
         va0 = inner.ravel().copy()
         Jp = _J(cfg, cfg["sigma"] + h * v[0], amps + h * v[1:1 + m], a0 + h * va0)
@@ -65,7 +67,10 @@ def test_gradient_against_central_differences_c5():
         fd = (Jp - Jm) / (2 * h)
         ad = float(grad @ v)
         # per direction: |grad.v - FD| / max(|FD|, 1e-3 ||grad|| ||v||) <= 1e-6
-        assert abs(ad - fd) / max(abs(fd), 1e-3 * np.linalg.norm(grad)) <= 1e-6, (t, ad, fd)
+        err = abs(ad - fd) / max(abs(fd), 1e-3 * np.linalg.norm(grad))
+        worst = max(worst, err)
+        note(f"fd direction {t}: adjoint {ad:.12e} fd {fd:.12e} rel {err:.2e}")
+    assert worst <= 1e-6
 
 
 def test_autograd_function():

@@ -26,8 +26,9 @@ def test_vcycle_matches_oracle(n, width, colour, nu, coarsest, a0):
     import paper_1304_1755_amd as sgbt
     note(f"vcycle n={n} width={width} {colour} {nu} coarsest={coarsest}")
     a0n = sg_inputs.a0_noise_field(n) if a0 else None
-    g = sgbt.Problem(n, 2, 1, 0.3, a0_nodal=a0n, colour=colour, nu1=nu[0], nu2=nu[1], coarsest=coarsest)
-    o = system.build_problem(n, 2, 1, 0.3, a0_nodal=a0n)
+    # m = 4, p = 3 gives P = 35 >= width (the V-cycle work space holds up to P columns)
+    g = sgbt.Problem(n, 4, 3, 0.3, a0_nodal=a0n, colour=colour, nu1=nu[0], nu2=nu[1], coarsest=coarsest)
+    o = system.build_problem(n, 4, 3, 0.3, a0_nodal=a0n)
     H = mg.Hierarchy(o.K[0], n, coarsest=coarsest, colour_mode=colour, nu1=nu[0], nu2=nu[1])
     f = sg_inputs.uniform_block(g.N, width, seed=11)
     ref = H.vcycle(f)
@@ -54,6 +55,16 @@ def test_preconditioners_match_oracle(cfg, kind):
     assert rel_max(Z, ref) < 1e-11
     Zm = to_host(g.precond(to_dev(R), kind=kind, prec=2))
     assert rel_max(Zm, ref) < 5e-5
+    g.close()
+
+
+def test_vcycle_width_above_P_is_rejected():
+    import paper_1304_1755_amd as sgbt
+    g = sgbt.Problem(16, 2, 1, 0.3)
+    f = torch.zeros((g.N, g.P + 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(sgbt.SGError) as e:
+        g.vcycle(f)
+    assert e.value.code == sgbt.SG_EINVAL
     g.close()
 
 

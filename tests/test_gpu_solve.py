@@ -53,8 +53,11 @@ def test_c2_bt_gmres_and_bd_pcg(sigma):
     g = sgbt.Problem(c["n"], c["m"], c["p"], sigma, c["corr_len"], colour="rb", nu1=1, nu2=1)
     o = system.build_problem(c["n"], c["m"], c["p"], sigma, c["corr_len"])
     H = mg.Hierarchy(o.K[0], c["n"], coarsest=8, colour_mode="rb", nu1=1, nu2=1)
+    note("oracle BT-FGMRES")
     A, _, io_t = _oracle_solve(o, "tri", H.vcycle)
+    note("oracle BD-PCG")
     _, _, io_d = _oracle_solve(o, "diag", H.vcycle, solver="pcg")
+    note("oracle reference solution")
     Ustar = system.solve_direct(o, A=A)
     F = o.rhs().ravel()
     for kind, solver, io in (("tri", "fgmres", io_t), ("diag", "pcg", io_d)):
@@ -74,6 +77,7 @@ def test_c3_copy_mixed_precision():
     g = sgbt.Problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"])
     o = system.build_problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"])
     A = system.assemble_A(o)
+    note("oracle reference solution c3_65")
     Ustar = system.solve_direct(o, A=A)
     F = o.rhs().ravel()
     for prec in (0, 2):
