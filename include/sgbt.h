@@ -156,7 +156,8 @@ int sg_qoi(sg_ctx* ctx, const double* U, double* q, double* J);
  * and the chain rule to sigma, the KL amplitudes s_k and the interior nodal
  * values of a0.  U: device doubles (a converged solution).  Outputs host:
  * J (1), dJ_dsigma (1), dJ_damp (m), dJ_da0 ((n-1)^2, interior nodes x-fastest).
- * adj_info: host, may be NULL. */
+ * adj_info: host, may be NULL.  Returns SG_ENOTCONV (outputs written) when
+ * the adjoint solve stopped at max_it above rtol. */
 int sg_qoi_grad(sg_ctx* ctx, const double* U, const sg_solve_opts* opts, double* J,
                 double* dJ_dsigma, double* dJ_damp, double* dJ_da0, sg_solve_info* adj_info);
 

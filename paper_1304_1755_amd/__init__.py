@@ -257,7 +257,7 @@ class Problem:
         dp = ctypes.POINTER(ctypes.c_double)
         _check(load_library().sg_qoi_grad(self._ctx, self._t(U, torch.float64, (self.N, self.P)), ctypes.byref(o),
                                           ctypes.byref(J), ctypes.byref(ds), damp.ctypes.data_as(dp),
-                                          da0.ctypes.data_as(dp), ctypes.byref(info)))
+                                          da0.ctypes.data_as(dp), ctypes.byref(info)), allow=(SG_OK, SG_ENOTCONV))
         return dict(J=J.value, dsigma=ds.value, damp=damp[:self.m].copy(), da0=da0, adj_info=info.as_dict())
 
     def sync(self):

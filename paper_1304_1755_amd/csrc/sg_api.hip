@@ -641,8 +641,9 @@ int sg_qoi_grad(sg_ctx* c, const double* U, const sg_solve_opts* opts, double* J
     SG_HIP_CHECK(vec_adj_rhs(c->stream, c->ws.wS, c->ws.qv + P, N, P, c->ws.g));
     sg_solve_opts o = *opts;
     o.use_x0 = 0;
-    rc = sg_solve(c, c->ws.g, c->ws.lam, &o, adj_info);
-    if (rc < 0) return rc;
+    // a solve stopped by max_it still yields a usable adjoint; report it in the status
+    const int solve_rc = sg_solve(c, c->ws.g, c->ws.lam, &o, adj_info);
+    if (solve_rc < 0 && solve_rc != SG_ENOTCONV) return solve_rc;
     SG_HIP_CHECK(vec_grad_cells(c->stream, c->plan_full.nslot, U, c->ws.lam, n, P, m, c->plan_full.d_off,
                                 c->plan_full.d_coef, c->ws.dc));
     double* params = c->ws.scal + 600;  // 1 + m values
@@ -656,7 +657,7 @@ int sg_qoi_grad(sg_ctx* c, const double* U, const sg_solve_opts* opts, double* J
     SG_HIP_CHECK(hipStreamSynchronize(c->stream));
     *dJ_dsigma = c->ws.host_scal[600];
     for (int k = 0; k < m; ++k) dJ_damp[k] = c->ws.host_scal[601 + k];
-    return SG_OK;
+    return solve_rc;
 }
 
 int sg_setup_host(const sg_options* opt, const double* a0_nodal, const double* kl_amp, double* cell_coeffs,

@@ -31,10 +31,20 @@ def test_gradient_matches_oracle_small():
     g.close()
 
 
+# Finite differences of J need J to be a smooth function of the parameters.
+# At 257^2 the relative residual cannot go below about 1e-11 (rounding in
+# A U ~ F with |A||U| >> |F|), so a tolerance-driven stop would make the
+# iteration count, and J, jump between the +h and -h solves.  The FD
+# evaluations therefore run a fixed number of FGMRES steps (one cycle, no
+# restart), which brings the residual to its rounding floor, and the
+# gradient is taken at a solution computed the same way.
+FIXED = dict(precond="tri", prec=0, restart=60, rtol=1e-30, max_it=60)
+
+
 def _J(cfg, sigma, amps, a0):
     import paper_1304_1755_amd as sgbt
     g = sgbt.Problem(cfg["n"], cfg["m"], cfg["p"], sigma, cfg["corr_len"], a0_nodal=a0, kl_amp=amps)
-    U, info = g.solve(**SOLVE)
+    U, info = g.solve(**FIXED)
     J, _ = g.qoi(U)
     g.close()
     return J
@@ -48,11 +58,12 @@ def test_gradient_against_central_differences_c5():
     a0 = sg_inputs.a0_noise_field(n)
     g = sgbt.Problem(n, m, cfg["p"], cfg["sigma"], cfg["corr_len"], a0_nodal=a0)
     amps = np.sqrt(np.array(g.kl_lambda))
-    U, info = g.solve(**SOLVE)
+    U, info = g.solve(**FIXED)
     note(f"c5 forward solve: {info['iters']} it, status {info['status']}, residual {info['rel_res_true']:.2e}")
-    assert info["rel_res_true"] < 1e-12
-    gr = g.qoi_grad(U, **SOLVE)
+    assert info["rel_res_true"] < 1e-10
+    gr = g.qoi_grad(U, **FIXED)
     note(f"c5 adjoint solve: {gr['adj_info']['iters']} it, residual {gr['adj_info']['rel_res_true']:.2e}")
+    assert gr["adj_info"]["rel_res_true"] < 1e-10
     g.close()
     grad = np.concatenate([[gr["dsigma"]], gr["damp"], gr["da0"]])
     dirs = sg_inputs.unit_directions(20, grad.size, seed=7)
