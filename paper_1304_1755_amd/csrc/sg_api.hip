@@ -251,10 +251,11 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
                 return rc;
             tm.rec(3, c->stream);
             tm.rec(4, c->stream);
-            // classical Gram-Schmidt, twice
+            // classical Gram-Schmidt, twice; the first update and the second
+            // projection share one pass over the basis
             SG_HIP_CHECK(vec_multidot(c->stream, c->ws.V, np, j + 1, c->ws.w, np, c->ws.partial, scal));
-            SG_HIP_CHECK(vec_update(c->stream, c->ws.V, np, j + 1, scal, c->ws.w, np, nullptr, nullptr));
-            SG_HIP_CHECK(vec_multidot(c->stream, c->ws.V, np, j + 1, c->ws.w, np, c->ws.partial, scal + 128));
+            SG_HIP_CHECK(vec_update_multidot(c->stream, c->ws.V, np, j + 1, scal, c->ws.w, np, c->ws.partial,
+                                             scal + 128));
             SG_HIP_CHECK(vec_update(c->stream, c->ws.V, np, j + 1, scal + 128, c->ws.w, np, c->ws.partial,
                                     scal + 256));
             tm.rec(5, c->stream);

@@ -15,6 +15,8 @@ hipError_t vec_multidot(hipStream_t s, const double* V, size_t stride, int nv, c
                         double* partial, double* out);
 hipError_t vec_update(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w, size_t len,
                       double* partial_sq, double* out_sq);
+hipError_t vec_update_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w,
+                               size_t len, double* partial, double* out);
 hipError_t vec_dot(hipStream_t s, const double* a, const double* b, size_t len, double* partial, double* out);
 hipError_t vec_scale(hipStream_t s, const double* src, double a, double* dst, size_t len);
 hipError_t vec_combine(hipStream_t s, const void* Z, int z_float, size_t stride, int nz, const double* y, double* x,

@@ -31,25 +31,62 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
-// partial[b][i] = sum over block b's elements of V_i[e] * w[e], i < nv (nv <= 16)
+constexpr int kVec = 32;  // basis vectors handled by one pass
+
+// partial[b][i] = sum over block b's elements of V_i[e] * w[e], i < nv (nv <= kVec)
 __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, size_t stride, int nv,
                                                   const double* __restrict__ w, size_t len,
                                                   double* __restrict__ partial) {
     __shared__ double sh[4];
-    double acc[16];
+    double acc[kVec];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    for (int i = 0; i < kVec; ++i) acc[i] = 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
         const double we = w[e];
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < kVec; ++i)
             if (i < nv) acc[i] = fma(V[(size_t)i * stride + e], we, acc[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < kVec; ++i) {
         if (i < nv) {  // uniform: keeps the loop unrolled and acc[] in registers
             const double t = block_sum(acc[i], sh);
-            if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 16 + i] = t;
+            if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kVec + i] = t;
+        }
+    }
+}
+
+// Second Gram-Schmidt pass fused with the first update:
+//   w <- w - sum_i h[i] V_i,  partial[b][i] = sum over block b of V_i[e] * w_new[e]
+__global__ void __launch_bounds__(256) k_update_dot(const double* __restrict__ V, size_t stride, int nv,
+                                                    const double* __restrict__ h, double* __restrict__ w,
+                                                    size_t len, double* __restrict__ partial) {
+    __shared__ double sh[4];
+    __shared__ double hs[kVec];
+    if (threadIdx.x < kVec) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[kVec];
+#pragma unroll
+    for (int i = 0; i < kVec; ++i) acc[i] = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
+        double v[kVec];
+        double we = w[e];
+#pragma unroll
+        for (int i = 0; i < kVec; ++i)
+            if (i < nv) {
+                v[i] = V[(size_t)i * stride + e];
+                we = fma(-hs[i], v[i], we);
+            }
+        w[e] = we;
+#pragma unroll
+        for (int i = 0; i < kVec; ++i)
+            if (i < nv) acc[i] = fma(v[i], we, acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kVec; ++i) {
+        if (i < nv) {
+            const double t = block_sum(acc[i], sh);
+            if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kVec + i] = t;
         }
     }
 }
@@ -71,14 +108,14 @@ __global__ void __launch_bounds__(256) k_update(const double* __restrict__ V, si
                                                 const double* __restrict__ h, double* __restrict__ w, size_t len,
                                                 double* __restrict__ partial_sq) {
     __shared__ double sh[4];
-    __shared__ double hs[16];
-    if (threadIdx.x < 16) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
+    __shared__ double hs[kVec];
+    if (threadIdx.x < kVec) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
     __syncthreads();
     double sq = 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
         double we = w[e];
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < kVec; ++i)
             if (i < nv) we = fma(-hs[i], V[(size_t)i * stride + e], we);
         w[e] = we;
         sq = fma(we, we, sq);
@@ -309,26 +346,38 @@ __global__ void k_grad_a0(const double* __restrict__ dc, int n, int m, double* _
 // ------------------------------------------------------------------ launchers
 hipError_t vec_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* w, size_t len,
                         double* partial, double* out) {
-    // nv may exceed 16: process the basis in chunks
-    for (int c0 = 0; c0 < nv; c0 += 16) {
-        const int cn = std::min(16, nv - c0);
+    // nv may exceed kVec: process the basis in chunks
+    for (int c0 = 0; c0 < nv; c0 += kVec) {
+        const int cn = std::min(kVec, nv - c0);
         hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(256), 0, s, V + (size_t)c0 * stride, stride, cn, w, len,
                            partial);
-        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, cn, 16, out + c0);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, cn, kVec, out + c0);
     }
     return hipGetLastError();
 }
 
 hipError_t vec_update(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w, size_t len,
                       double* partial_sq, double* out_sq) {
-    for (int c0 = 0; c0 < nv; c0 += 16) {
-        const int cn = std::min(16, nv - c0);
-        const bool last = c0 + 16 >= nv;
-        hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, s, V + (size_t)c0 * stride, stride, cn, h + c0, w,
-                           len, (last && partial_sq) ? partial_sq : nullptr);
+    for (int c0 = 0; c0 < nv; c0 += kVec) {
+        const int cn = std::min(kVec, nv - c0);
+        const bool last = c0 + kVec >= nv;
+        hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, s, V + (size_t)c0 * stride, stride, cn, h + c0,
+                           w, len, (last && partial_sq) ? partial_sq : nullptr);
     }
     if (partial_sq && out_sq)
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial_sq, kRedBlocks, 1, 1, out_sq);
+    return hipGetLastError();
+}
+
+hipError_t vec_update_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w,
+                               size_t len, double* partial, double* out) {
+    if (nv > kVec) {  // unfused fallback for long bases
+        hipError_t e = vec_update(s, V, stride, nv, h, w, len, nullptr, nullptr);
+        if (e != hipSuccess) return e;
+        return vec_multidot(s, V, stride, nv, w, len, partial, out);
+    }
+    hipLaunchKernelGGL(k_update_dot, dim3(kRedBlocks), dim3(256), 0, s, V, stride, nv, h, w, len, partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, nv, kVec, out);
     return hipGetLastError();
 }
 
