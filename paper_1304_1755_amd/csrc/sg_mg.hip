@@ -52,11 +52,16 @@ __global__ void k_cast(const Ts* __restrict__ src, int lds, Td* __restrict__ dst
 // snap == nullptr: in-place update (four colours never touch each other).
 // snap != nullptr: red/black first pass, new values are written to `snap`
 // (a staging buffer) and copied back by k_copy_colour.
-template <typename T>
+// first != 0: the first sweep after a zero initial guess.  Every node of a
+// colour that has not been updated yet in this sweep still holds zero, so
+// those neighbours are skipped and u needs no clearing beforehand.  (For
+// red/black the same-colour diagonal neighbours are also still zero.)
+template <typename T, bool WAVE_NODE>
 __global__ void k_gs(const T* __restrict__ sten, T* __restrict__ u, int ldu, const T* __restrict__ f, int ldf,
-                     T* __restrict__ out, int ldo, int nx, int width, int rb, int q, int nxc, int nyc) {
+                     T* __restrict__ out, int ldo, int nx, int width, int rb, int q, int nxc, int nyc, int first) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
-    const int t = blockIdx.x * blockDim.y + threadIdx.y;
+    int t = blockIdx.x * blockDim.y + threadIdx.y;
+    if (WAVE_NODE) t = __builtin_amdgcn_readfirstlane(t);  // one node per wavefront: scalar stencil loads
     if (mode >= width || t >= nxc * nyc) return;
     const int j = t / nxc, i = t - j * nxc;
     int x, y;
@@ -80,6 +85,11 @@ __global__ void k_gs(const T* __restrict__ sten, T* __restrict__ u, int ldu, con
             if (dx == 0 && dy == 0) continue;
             const int xx = x + dx;
             if (xx < 0 || xx >= nx) continue;
+            if (first) {
+                // colour of the neighbour from its grid indices (xx+1, yy+1)
+                const int qn = rb ? ((xx + yy) & 1) : (((xx + 1) & 1) + 2 * ((yy + 1) & 1));
+                if (qn >= q) continue;
+            }
             acc -= st[(dy + 1) * 3 + (dx + 1)] * u[((size_t)yy * nx + xx) * ldu + mode];
         }
     }
@@ -189,6 +199,180 @@ __global__ void k_coarse(const double* __restrict__ kinv, const T* __restrict__ 
     }
 }
 
+// ----------------------------------------------------------------- coarse grids in LDS
+// The grids at and below kFusedNx interior nodes per side are cycled by a
+// single launch: one workgroup per right-hand-side column keeps u and f of
+// every coarse level (and one residual array) in LDS and runs smoothing,
+// residual, restriction, the coarsest solve, prolongation and
+// post-smoothing with workgroup barriers between passes.  This replaces
+// about twenty launches per coarse level.
+constexpr int kMaxFusedLevels = 8;
+
+template <typename T>
+struct FusedLevels {
+    int nlev;                       // levels in the fused part, the last is the coarsest
+    int nx[kMaxFusedLevels];
+    int off[kMaxFusedLevels];       // LDS element offset of u_l (f_l follows at off + N_l)
+    const T* sten[kMaxFusedLevels];
+    int roff;                       // LDS element offset of the residual / staging array
+};
+
+template <typename T>
+constexpr int fused_nx_max() { return sizeof(T) == 4 ? 63 : 31; }
+
+template <typename T>
+__device__ void lds_smooth(const T* __restrict__ st, T* u, const T* f, T* stage, int nx, bool rb, bool reverse,
+                           int nu) {
+    const int ncol = rb ? 2 : 4;
+    for (int sweep = 0; sweep < nu; ++sweep)
+        for (int qi = 0; qi < ncol; ++qi) {
+            const int q = reverse ? ncol - 1 - qi : qi;
+            int nxc, nyc;
+            if (rb) { nxc = (nx + 1) / 2; nyc = nx; }
+            else { nxc = (nx - (((q & 1) ^ 1)) + 1) / 2; nyc = (nx - (((q >> 1) ^ 1)) + 1) / 2; }
+            for (int t = threadIdx.x; t < nxc * nyc; t += blockDim.x) {
+                const int j = t / nxc, i = t - j * nxc;
+                int x, y;
+                if (rb) { y = j; x = ((q + y) & 1) + 2 * i; if (x >= nx) continue; }
+                else { x = ((q & 1) ^ 1) + 2 * i; y = ((q >> 1) ^ 1) + 2 * j; }
+                const int node = y * nx + x;
+                const T* s9 = st + (size_t)node * 9;
+                T acc = f[node];
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int yy = y + dy;
+                    if (yy < 0 || yy >= nx) continue;
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (dx == 0 && dy == 0) continue;
+                        const int xx = x + dx;
+                        if (xx < 0 || xx >= nx) continue;
+                        acc -= s9[(dy + 1) * 3 + (dx + 1)] * u[yy * nx + xx];
+                    }
+                }
+                const T val = acc / s9[4];
+                if (rb) stage[node] = val; else u[node] = val;
+            }
+            __syncthreads();
+            if (rb) {
+                for (int t = threadIdx.x; t < nxc * nyc; t += blockDim.x) {
+                    const int y = t / nxc, i = t - y * nxc;
+                    const int x = ((q + y) & 1) + 2 * i;
+                    if (x < nx) u[y * nx + x] = stage[y * nx + x];
+                }
+                __syncthreads();
+            }
+        }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const double* __restrict__ kinv,
+                                                      const T* __restrict__ fin, int ldf, T* __restrict__ uout,
+                                                      int ldu, int nu1, int nu2, int rb) {
+    extern __shared__ char smem_raw[];
+    T* lds = (T*)smem_raw;
+    T* r = lds + fl.roff;
+    const int col = blockIdx.x;
+    const int L = fl.nlev - 1;
+    {
+        const int N0 = fl.nx[0] * fl.nx[0];
+        T* f0 = lds + fl.off[0] + N0;
+        for (int i = threadIdx.x; i < N0; i += blockDim.x) f0[i] = fin[(size_t)i * ldf + col];
+    }
+    __syncthreads();
+    for (int l = 0; l < L; ++l) {
+        const int nx = fl.nx[l], N = nx * nx;
+        T* u = lds + fl.off[l];
+        T* f = u + N;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) u[i] = T(0);
+        __syncthreads();
+        lds_smooth<T>(fl.sten[l], u, f, r, nx, rb, false, nu1);
+        // residual r = f - K u
+        for (int node = threadIdx.x; node < N; node += blockDim.x) {
+            const int y = node / nx, x = node - y * nx;
+            const T* s9 = fl.sten[l] + (size_t)node * 9;
+            T acc = f[node];
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int yy = y + dy;
+                if (yy < 0 || yy >= nx) continue;
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int xx = x + dx;
+                    if (xx < 0 || xx >= nx) continue;
+                    acc -= s9[(dy + 1) * 3 + (dx + 1)] * u[yy * nx + xx];
+                }
+            }
+            r[node] = acc;
+        }
+        __syncthreads();
+        // restriction to the next level's right-hand side
+        const int nxc = fl.nx[l + 1], Nc = nxc * nxc;
+        T* fc = lds + fl.off[l + 1] + Nc;
+        for (int node = threadIdx.x; node < Nc; node += blockDim.x) {
+            const int Y = node / nxc, X = node - Y * nxc;
+            const int fx = 2 * X + 1, fy = 2 * Y + 1;
+            T acc = T(0);
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const T wy = dy == 0 ? T(1) : T(0.5);
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const T wx = dx == 0 ? T(1) : T(0.5);
+                    acc += wx * wy * r[(fy + dy) * nx + (fx + dx)];
+                }
+            }
+            fc[node] = acc;
+        }
+        __syncthreads();
+    }
+    {
+        // coarsest grid: u = K^{-1} f with the inverse precomputed in double
+        const int nx = fl.nx[L], N = nx * nx;
+        T* u = lds + fl.off[L];
+        const T* f = u + N;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const double* row = kinv + (size_t)i * N;
+            double acc = 0.0;
+            for (int j = 0; j < N; ++j) acc = fma(row[j], (double)f[j], acc);
+            u[i] = (T)acc;
+        }
+        __syncthreads();
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        const int nx = fl.nx[l], N = nx * nx, nxc = fl.nx[l + 1];
+        T* u = lds + fl.off[l];
+        const T* f = u + N;
+        const T* ec = lds + fl.off[l + 1];
+        for (int node = threadIdx.x; node < N; node += blockDim.x) {
+            const int y = node / nx, x = node - y * nx;
+            int cx0, cx1, cy0, cy1;
+            T wx, wy;
+            if (x & 1) { cx0 = cx1 = (x - 1) >> 1; wx = T(1); } else { cx0 = (x >> 1) - 1; cx1 = x >> 1; wx = T(0.5); }
+            if (y & 1) { cy0 = cy1 = (y - 1) >> 1; wy = T(1); } else { cy0 = (y >> 1) - 1; cy1 = y >> 1; wy = T(0.5); }
+            T acc = T(0);
+            const int ncx = (cx0 == cx1) ? 1 : 2, ncy = (cy0 == cy1) ? 1 : 2;
+            for (int b = 0; b < ncy; ++b) {
+                const int cy = b ? cy1 : cy0;
+                if (cy < 0 || cy >= nxc) continue;
+                for (int a = 0; a < ncx; ++a) {
+                    const int cx = a ? cx1 : cx0;
+                    if (cx < 0 || cx >= nxc) continue;
+                    acc += ec[cy * nxc + cx];
+                }
+            }
+            u[node] += wx * wy * acc;
+        }
+        __syncthreads();
+        lds_smooth<T>(fl.sten[l], u, f, r, nx, rb, true, nu2);
+    }
+    {
+        const int N0 = fl.nx[0] * fl.nx[0];
+        const T* u0 = lds + fl.off[0];
+        for (int i = threadIdx.x; i < N0; i += blockDim.x) uout[(size_t)i * ldu + col] = u0[i];
+    }
+}
+
 inline dim3 grid2(int rows, int width, const Tile& tl) {
     return dim3((rows + tl.ty - 1) / tl.ty, (width + tl.tx - 1) / tl.tx);
 }
@@ -211,7 +395,19 @@ struct LevelPtr<float> {
 };
 
 template <typename T>
-void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, bool reverse, const Tile& tl) {
+void launch_gs(const Tile& tl, dim3 g, hipStream_t st, const T* sten, T* u, int ldu, const T* f, int ldf, T* out,
+               int ldo, int nx, int width, int rb, int q, int nxc, int nyc, int first) {
+    if (tl.tx == 64)
+        hipLaunchKernelGGL((k_gs<T, true>), g, dim3(tl.tx, tl.ty), 0, st, sten, u, ldu, f, ldf, out, ldo, nx, width,
+                           rb, q, nxc, nyc, first);
+    else
+        hipLaunchKernelGGL((k_gs<T, false>), g, dim3(tl.tx, tl.ty), 0, st, sten, u, ldu, f, ldf, out, ldo, nx, width,
+                           rb, q, nxc, nyc, first);
+}
+
+template <typename T>
+void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, bool reverse, const Tile& tl,
+            bool first) {
     Level& lv = c->levels[l];
     const int nx = lv.nx;
     const bool rb = c->opt.colour_mode == SG_COLOUR_RB;
@@ -221,13 +417,13 @@ void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, boo
         if (!rb) {
             const int px = (q & 1) ^ 1, py = (q >> 1) ^ 1;
             const int nxc = (nx - px + 1) / 2, nyc = (nx - py + 1) / 2;
-            hipLaunchKernelGGL(k_gs<T>, grid2(nxc * nyc, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                               LevelPtr<T>::s(lv), u, ldu, f, ldf, (T*)nullptr, 0, nx, width, 0, q, nxc, nyc);
+            launch_gs<T>(tl, grid2(nxc * nyc, width, tl), c->stream, LevelPtr<T>::s(lv), u, ldu, f, ldf, nullptr, 0,
+                         nx, width, 0, q, nxc, nyc, first ? 1 : 0);
         } else {
             const int nxc = (nx + 1) / 2, nyc = nx;
             T* stage = LevelPtr<T>::r(lv);  // residual buffer is free during smoothing
-            hipLaunchKernelGGL(k_gs<T>, grid2(nxc * nyc, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                               LevelPtr<T>::s(lv), u, ldu, f, ldf, stage, width, nx, width, 1, q, nxc, nyc);
+            launch_gs<T>(tl, grid2(nxc * nyc, width, tl), c->stream, LevelPtr<T>::s(lv), u, ldu, f, ldf, stage,
+                         width, nx, width, 1, q, nxc, nyc, first ? 1 : 0);
             hipLaunchKernelGGL(k_copy_colour<T>, grid2(nxc * nyc, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
                                (const T*)stage, width, u, ldu, nx, width, q, nxc, nyc);
         }
@@ -238,41 +434,61 @@ template <typename T>
 int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     const Tile tl = tile_for(width);
     const int L = (int)c->levels.size() - 1;
-    const size_t nc_sh = (size_t)c->levels[L].N * sizeof(double);
-    if (L == 0) {
-        hipLaunchKernelGGL(k_coarse<T>, dim3(width), dim3(256), nc_sh, c->stream, c->kinv, f0, ldf0, u0, ldu0,
-                           c->levels[0].N);
-        return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
-    }
-    for (int l = 0; l < L; ++l) {
+    // first level handled by the fused LDS kernel (-1: none fits, coarsest solved by k_coarse)
+    int Lc = -1;
+    for (int l = 0; l <= L; ++l)
+        if (c->levels[l].nx <= fused_nx_max<T>()) { Lc = l; break; }
+    const int Ltop = Lc >= 0 ? Lc : L;  // levels above Ltop are cycled by separate launches
+    auto fptr = [&](int l) -> const T* { return l == 0 ? f0 : LevelPtr<T>::f(c->levels[l]); };
+    auto fld = [&](int l) { return l == 0 ? ldf0 : width; };
+    auto uptr = [&](int l) -> T* { return l == 0 ? u0 : LevelPtr<T>::u(c->levels[l]); };
+    auto uld = [&](int l) { return l == 0 ? ldu0 : width; };
+    for (int l = 0; l < Ltop; ++l) {
         Level& lv = c->levels[l];
-        const T* f = l == 0 ? f0 : LevelPtr<T>::f(lv);
-        const int ldf = l == 0 ? ldf0 : width;
-        T* u = l == 0 ? u0 : LevelPtr<T>::u(lv);
-        const int ldu = l == 0 ? ldu0 : width;
-        hipLaunchKernelGGL(k_fill<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream, u, ldu, lv.N, width);
-        for (int s = 0; s < c->opt.nu1; ++s) smooth<T>(c, l, u, ldu, f, ldf, width, false, tl);
+        T* u = uptr(l);
+        // zero initial guess: the first sweep skips not-yet-updated neighbours, so u needs no clearing
+        if (c->opt.nu1 == 0)
+            hipLaunchKernelGGL(k_fill<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream, u, uld(l), lv.N,
+                               width);
+        for (int s = 0; s < c->opt.nu1; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, false, tl, s == 0);
         T* r = LevelPtr<T>::r(lv);
         hipLaunchKernelGGL(k_residual<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                           LevelPtr<T>::s(lv), (const T*)u, ldu, f, ldf, r, width, lv.nx, width);
+                           LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), r, width, lv.nx, width);
         Level& lc = c->levels[l + 1];
         hipLaunchKernelGGL(k_restrict<T>, grid2(lc.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
                            (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width);
     }
-    {
+    if (Lc >= 0) {
+        FusedLevels<T> fl{};
+        fl.nlev = L - Lc + 1;
+        if (fl.nlev > kMaxFusedLevels) {
+            set_error("vcycle: too many coarse levels");
+            return SG_EINVAL;
+        }
+        int off = 0;
+        for (int i = 0; i < fl.nlev; ++i) {
+            const Level& lv = c->levels[Lc + i];
+            fl.nx[i] = lv.nx;
+            fl.off[i] = off;
+            fl.sten[i] = LevelPtr<T>::s(lv);
+            off += 2 * lv.N;
+        }
+        fl.roff = off;
+        off += c->levels[Lc].N;
+        hipLaunchKernelGGL(k_vcycle_fused<T>, dim3(width), dim3(512), (size_t)off * sizeof(T), c->stream, fl,
+                           (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2,
+                           c->opt.colour_mode == SG_COLOUR_RB ? 1 : 0);
+    } else {
         Level& lc = c->levels[L];
-        hipLaunchKernelGGL(k_coarse<T>, dim3(width), dim3(256), nc_sh, c->stream, c->kinv,
-                           (const T*)LevelPtr<T>::f(lc), width, LevelPtr<T>::u(lc), width, lc.N);
+        hipLaunchKernelGGL(k_coarse<T>, dim3(width), dim3(256), (size_t)lc.N * sizeof(double), c->stream, c->kinv,
+                           fptr(L), fld(L), uptr(L), uld(L), lc.N);
     }
-    for (int l = L - 1; l >= 0; --l) {
+    for (int l = Ltop - 1; l >= 0; --l) {
         Level& lv = c->levels[l];
-        const T* f = l == 0 ? f0 : LevelPtr<T>::f(lv);
-        const int ldf = l == 0 ? ldf0 : width;
-        T* u = l == 0 ? u0 : LevelPtr<T>::u(lv);
-        const int ldu = l == 0 ? ldu0 : width;
+        T* u = uptr(l);
         hipLaunchKernelGGL(k_prolong_add<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                           (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, ldu, lv.nx, width);
-        for (int s = 0; s < c->opt.nu2; ++s) smooth<T>(c, l, u, ldu, f, ldf, width, true, tl);
+                           (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width);
+        for (int s = 0; s < c->opt.nu2; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, tl, false);
     }
     return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
 }

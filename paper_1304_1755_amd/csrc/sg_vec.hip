@@ -69,18 +69,18 @@ __global__ void __launch_bounds__(256) k_update_dot(const double* __restrict__ V
 #pragma unroll
     for (int i = 0; i < kVec; ++i) acc[i] = 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
-        double v[kVec];
         double we = w[e];
 #pragma unroll
         for (int i = 0; i < kVec; ++i)
-            if (i < nv) {
-                v[i] = V[(size_t)i * stride + e];
-                we = fma(-hs[i], v[i], we);
-            }
+            if (i < nv) we = fma(-hs[i], V[(size_t)i * stride + e], we);
         w[e] = we;
+        // the basis entries were just read by this thread, so the second read
+        // hits the cache; the barrier stops the compiler from keeping all of
+        // them in registers (which would cut occupancy)
+        __asm__ __volatile__("" ::: "memory");
 #pragma unroll
         for (int i = 0; i < kVec; ++i)
-            if (i < nv) acc[i] = fma(v[i], we, acc[i]);
+            if (i < nv) acc[i] = fma(V[(size_t)i * stride + e], we, acc[i]);
     }
 #pragma unroll
     for (int i = 0; i < kVec; ++i) {
