@@ -46,12 +46,15 @@ int upload_plan(sg_ctx* c, const PlanHost& ph, Plan& pl) {
     pl.W_out = ph.W_out;
     pl.nslot = ph.nslot;
     pl.self = ph.self;
+    for (int s = 0; s < kMaxSlots; ++s) pl.nlist[s] = s < (int)ph.nlist.size() ? ph.nlist[s] : 0;
     int rc = upload(c, &pl.d_off, ph.off);
     if (rc) return rc;
     return upload(c, &pl.d_coef, ph.coef);
 }
 
 size_t NP(const sg_ctx* c) { return (size_t)c->hs.N * c->hs.P; }
+// stride of the Krylov basis: NP rounded up so every basis vector starts 512-byte aligned
+size_t NPpad(const sg_ctx* c) { return (NP(c) + 63) / 64 * 64; }
 
 int ensure_mg(sg_ctx* c, int is_float) {
     const int P = c->hs.P;
@@ -100,10 +103,10 @@ int ensure_krylov(sg_ctx* c, int restart, int z_float) {
         if (rc) return rc;
     }
     if (c->ws.restart < restart) {
-        rc = dalloc(c, &c->ws.V, (size_t)(restart + 1) * np);
+        rc = dalloc(c, &c->ws.V, (size_t)(restart + 1) * NPpad(c));
         if (rc) return rc;
         double* z = nullptr;  // sized for doubles, so it also holds a float basis
-        rc = dalloc(c, &z, (size_t)restart * np);
+        rc = dalloc(c, &z, (size_t)restart * NPpad(c));
         if (rc) return rc;
         c->ws.Z = z;
         c->ws.restart = restart;
@@ -207,8 +210,9 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
     double* scal = c->ws.scal;
     double* hs = c->ws.host_scal;
     const size_t zes = zf ? sizeof(float) : sizeof(double);
-    auto Vj = [&](int j) { return c->ws.V + (size_t)j * np; };
-    auto Zj = [&](int j) { return (void*)((char*)c->ws.Z + (size_t)j * np * zes); };
+    const size_t vs = NPpad(c);
+    auto Vj = [&](int j) { return c->ws.V + (size_t)j * vs; };
+    auto Zj = [&](int j) { return (void*)((char*)c->ws.Z + (size_t)j * vs * zes); };
 
     SG_HIP_CHECK(vec_dot(c->stream, F, F, np, c->ws.partial, scal));
     if ((rc = fetch(c, scal, 1))) return rc;
@@ -253,10 +257,10 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
             tm.rec(4, c->stream);
             // classical Gram-Schmidt, twice; the first update and the second
             // projection share one pass over the basis
-            SG_HIP_CHECK(vec_multidot(c->stream, c->ws.V, np, j + 1, c->ws.w, np, c->ws.partial, scal));
-            SG_HIP_CHECK(vec_update_multidot(c->stream, c->ws.V, np, j + 1, scal, c->ws.w, np, c->ws.partial,
+            SG_HIP_CHECK(vec_multidot(c->stream, c->ws.V, vs, j + 1, c->ws.w, np, c->ws.partial, scal));
+            SG_HIP_CHECK(vec_update_multidot(c->stream, c->ws.V, vs, j + 1, scal, c->ws.w, np, c->ws.partial,
                                              scal + 128));
-            SG_HIP_CHECK(vec_update(c->stream, c->ws.V, np, j + 1, scal + 128, c->ws.w, np, c->ws.partial,
+            SG_HIP_CHECK(vec_update(c->stream, c->ws.V, vs, j + 1, scal + 128, c->ws.w, np, c->ws.partial,
                                     scal + 256));
             tm.rec(5, c->stream);
             SG_HIP_CHECK(hipMemcpyAsync(hs, scal, 257 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -297,7 +301,7 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
         }
         std::memcpy(hs + 512, y.data(), k * sizeof(double));
         SG_HIP_CHECK(hipMemcpyAsync(scal + 512, hs + 512, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        SG_HIP_CHECK(vec_combine(c->stream, c->ws.Z, zf, np, k, scal + 512, X, np));
+        SG_HIP_CHECK(vec_combine(c->stream, c->ws.Z, zf, vs, k, scal + 512, X, np));
         if ((rc = launch_apply(c, c->plan_full, X, 0, F, c->ws.w, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
         SG_HIP_CHECK(vec_dot(c->stream, c->ws.w, c->ws.w, np, c->ws.partial, scal));
         if ((rc = fetch(c, scal, 1))) return rc;

@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(NS * 64)
 k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int ldr,
            Tout* __restrict__ Y, int ldy, const double* __restrict__ cell,
            const uint32_t* __restrict__ toff, const double* __restrict__ tcoef, int n, int W_in,
-           int W_out, int self, int seg, int nseg) {
+           int W_out, int self, int seg, int nseg, int4 nlists) {
     constexpr int MM = M > 0 ? M : 1;
     constexpr int LANES = NS * 64;
     constexpr int BUF = MM * LANES + 2;
@@ -71,13 +71,15 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     const bool has_in = s * 64 < W_in, has_out = s * 64 < W_out;  // uniform
     const bool vin = t < W_in, vout = t < W_out;
 
+    // this lane's partner list (entries 2j and 2j+1 share one index word)
+    const int nl = s == 0 ? nlists.x : s == 1 ? nlists.y : s == 2 ? nlists.z : nlists.w;  // uniform
     uint32_t off[MM];
-    double cu[MM], cd[MM];
+    double ce[2 * MM];
 #pragma unroll
-    for (int k = 0; k < MM; ++k) {
-        off[k] = M > 0 ? toff[t * MM + k] : 0u;
-        cu[k] = M > 0 ? tcoef[2 * (t * MM + k)] : 0.0;
-        cd[k] = M > 0 ? tcoef[2 * (t * MM + k) + 1] : 0.0;
+    for (int j = 0; j < MM; ++j) {
+        off[j] = M > 0 ? toff[t * MM + j] : 0u;
+        ce[2 * j] = M > 0 ? tcoef[t * 2 * MM + 2 * j] : 0.0;
+        ce[2 * j + 1] = M > 0 ? tcoef[t * 2 * MM + 2 * j + 1] : 0.0;
     }
     if (threadIdx.x == 0) {
         S[0][MM * LANES] = 0.0;  // shared zero entry for absent partners
@@ -126,9 +128,9 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
         if (has_out) {
             double acc = self ? s0 : 0.0;
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                acc = fma(cu[k], B[off[k] & 0xFFFFu], acc);
-                acc = fma(cd[k], B[off[k] >> 16], acc);
+            for (int j = 0; j < M; ++j) {
+                if (2 * j < nl) acc = fma(ce[2 * j], B[off[j] & 0xFFFFu], acc);
+                if (2 * j + 1 < nl) acc = fma(ce[2 * j + 1], B[off[j] >> 16], acc);
             }
             if (vout) {
                 const size_t node = (size_t)y * nx + x;
@@ -153,7 +155,7 @@ hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, cons
     const int blocks = nx * nseg;
     hipLaunchKernelGGL((k_sg_apply<M, NS, Tin, Tout>), dim3(blocks), dim3(NS * 64), 0, st,
                        (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out, pl.self,
-                       seg, nseg);
+                       seg, nseg, make_int4(pl.nlist[0], pl.nlist[1], pl.nlist[2], pl.nlist[3]));
     return hipGetLastError();
 }
 

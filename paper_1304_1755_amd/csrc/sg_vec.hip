@@ -33,22 +33,37 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 constexpr int kVec = 32;  // basis vectors handled by one pass
 
-// partial[b][i] = sum over block b's elements of V_i[e] * w[e], i < nv (nv <= kVec)
+// Basis passes work on pairs of doubles (16-byte loads): the basis stride
+// must be even (the launchers check it); an odd length leaves one last
+// element, handled by one thread.
+
+// partial[b][i] = sum over block b's elements of V_i[e] * w[e], i < nv (nv <= NV)
+template <int NV>
 __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, size_t stride, int nv,
                                                   const double* __restrict__ w, size_t len,
                                                   double* __restrict__ partial) {
     __shared__ double sh[4];
-    double acc[kVec];
+    double acc[NV];
 #pragma unroll
-    for (int i = 0; i < kVec; ++i) acc[i] = 0.0;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
-        const double we = w[e];
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    const size_t half = len / 2;
+    const double2* w2 = (const double2*)w;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < half; e += (size_t)gridDim.x * blockDim.x) {
+        const double2 we = w2[e];
 #pragma unroll
-        for (int i = 0; i < kVec; ++i)
-            if (i < nv) acc[i] = fma(V[(size_t)i * stride + e], we, acc[i]);
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) {
+                const double2 vv = ((const double2*)(V + (size_t)i * stride))[e];
+                acc[i] = fma(vv.x, we.x, fma(vv.y, we.y, acc[i]));
+            }
+    }
+    if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // odd length: last element
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) acc[i] = fma(V[(size_t)i * stride + len - 1], w[len - 1], acc[i]);
     }
 #pragma unroll
-    for (int i = 0; i < kVec; ++i) {
+    for (int i = 0; i < NV; ++i) {
         if (i < nv) {  // uniform: keeps the loop unrolled and acc[] in registers
             const double t = block_sum(acc[i], sh);
             if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kVec + i] = t;
@@ -56,34 +71,48 @@ __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, 
     }
 }
 
-// Second Gram-Schmidt pass fused with the first update:
+// Second Gram-Schmidt pass fused with the first update (short bases, NV <= 16):
 //   w <- w - sum_i h[i] V_i,  partial[b][i] = sum over block b of V_i[e] * w_new[e]
+template <int NV>
 __global__ void __launch_bounds__(256) k_update_dot(const double* __restrict__ V, size_t stride, int nv,
                                                     const double* __restrict__ h, double* __restrict__ w,
                                                     size_t len, double* __restrict__ partial) {
     __shared__ double sh[4];
-    __shared__ double hs[kVec];
-    if (threadIdx.x < kVec) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
+    __shared__ double hs[NV];
+    if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
     __syncthreads();
-    double acc[kVec];
+    double acc[NV];
 #pragma unroll
-    for (int i = 0; i < kVec; ++i) acc[i] = 0.0;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
-        double we = w[e];
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    const size_t half = len / 2;
+    double2* w2 = (double2*)w;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < half; e += (size_t)gridDim.x * blockDim.x) {
+        double2 v[NV];
+        double2 we = w2[e];
 #pragma unroll
-        for (int i = 0; i < kVec; ++i)
-            if (i < nv) we = fma(-hs[i], V[(size_t)i * stride + e], we);
-        w[e] = we;
-        // the basis entries were just read by this thread, so the second read
-        // hits the cache; the barrier stops the compiler from keeping all of
-        // them in registers (which would cut occupancy)
-        __asm__ __volatile__("" ::: "memory");
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) {
+                v[i] = ((const double2*)(V + (size_t)i * stride))[e];
+                we.x = fma(-hs[i], v[i].x, we.x);
+                we.y = fma(-hs[i], v[i].y, we.y);
+            }
+        w2[e] = we;
 #pragma unroll
-        for (int i = 0; i < kVec; ++i)
-            if (i < nv) acc[i] = fma(V[(size_t)i * stride + e], we, acc[i]);
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) acc[i] = fma(v[i].x, we.x, fma(v[i].y, we.y, acc[i]));
+    }
+    if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // odd length: last element
+        double we = w[len - 1];
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) we = fma(-hs[i], V[(size_t)i * stride + len - 1], we);
+        w[len - 1] = we;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) acc[i] = fma(V[(size_t)i * stride + len - 1], we, acc[i]);
     }
 #pragma unroll
-    for (int i = 0; i < kVec; ++i) {
+    for (int i = 0; i < NV; ++i) {
         if (i < nv) {
             const double t = block_sum(acc[i], sh);
             if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kVec + i] = t;
@@ -112,12 +141,26 @@ __global__ void __launch_bounds__(256) k_update(const double* __restrict__ V, si
     if (threadIdx.x < kVec) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
     __syncthreads();
     double sq = 0.0;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
-        double we = w[e];
+    const size_t half = len / 2;
+    double2* w2 = (double2*)w;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < half; e += (size_t)gridDim.x * blockDim.x) {
+        double2 we = w2[e];
 #pragma unroll
         for (int i = 0; i < kVec; ++i)
-            if (i < nv) we = fma(-hs[i], V[(size_t)i * stride + e], we);
-        w[e] = we;
+            if (i < nv) {
+                const double2 vv = ((const double2*)(V + (size_t)i * stride))[e];
+                we.x = fma(-hs[i], vv.x, we.x);
+                we.y = fma(-hs[i], vv.y, we.y);
+            }
+        w2[e] = we;
+        sq = fma(we.x, we.x, fma(we.y, we.y, sq));
+    }
+    if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // odd length: last element
+        double we = w[len - 1];
+#pragma unroll
+        for (int i = 0; i < kVec; ++i)
+            if (i < nv) we = fma(-hs[i], V[(size_t)i * stride + len - 1], we);
+        w[len - 1] = we;
         sq = fma(we, we, sq);
     }
     if (partial_sq) {
@@ -270,31 +313,26 @@ __global__ void __launch_bounds__(256) k_grad_cells(const double* __restrict__ U
     if (lane == 0) T[4 * LANES] = 0.0;
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __asm__ __volatile__("" ::: "memory");
+    // partner lists of the full coupling plan: entry i of lane a is the LDS
+    // element k*lanes + b of a partner b = a +- e_k with coefficient G_k(a, b)
     const uint32_t zero = (uint32_t)(m * LANES);
-    for (int k = 0; k < m; ++k) {
-        double ak = 0.0;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int a = s * 64 + lane;
-            if (a >= P) continue;
-            const size_t ti = (size_t)a * m + k;
-            const uint32_t o = toff[ti];
-            const uint32_t iu = o & 0xFFFFu, id = o >> 16;
-            const double cu = tcoef[2 * ti], cd = tcoef[2 * ti + 1];
-            if (iu != zero) {
-                const int b = (int)iu - k * LANES;
+    for (int s = 0; s < NS; ++s) {
+        const int a = s * 64 + lane;
+        if (a >= P) continue;
+        for (int i = 0; i < 2 * m; ++i) {
+            const uint32_t w = toff[(size_t)a * m + i / 2];
+            const uint32_t idx = (i & 1) ? (w >> 16) : (w & 0xFFFFu);
+            if (idx == zero) continue;
+            const int k = (int)idx / LANES, b = (int)idx - k * LANES;
+            const double g = tcoef[(size_t)a * 2 * m + i];
+            double dotv = 0.0;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) ak = fma(cu * l[s][v], T[v * LANES + b], ak);
-            }
-            if (id != zero) {
-                const int b = (int)id - k * LANES;
+            for (int v = 0; v < 4; ++v) dotv = fma(l[s][v], T[v * LANES + b], dotv);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) ak = fma(cd * l[s][v], T[v * LANES + b], ak);
-            }
+            for (int kk = 1; kk <= kMaxM; ++kk)
+                if (kk == k + 1) acc[kk] = fma(g, dotv, acc[kk]);
         }
-#pragma unroll
-        for (int kk = 1; kk <= kMaxM; ++kk)
-            if (kk == k + 1) acc[kk] = ak;
     }
 #pragma unroll
     for (int k = 0; k <= kMaxM; ++k) {
@@ -346,11 +384,17 @@ __global__ void k_grad_a0(const double* __restrict__ dc, int n, int m, double* _
 // ------------------------------------------------------------------ launchers
 hipError_t vec_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* w, size_t len,
                         double* partial, double* out) {
+    if (stride & 1) return hipErrorInvalidValue;  // pairs of doubles need an even basis stride
     // nv may exceed kVec: process the basis in chunks
     for (int c0 = 0; c0 < nv; c0 += kVec) {
         const int cn = std::min(kVec, nv - c0);
-        hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(256), 0, s, V + (size_t)c0 * stride, stride, cn, w, len,
-                           partial);
+        const double* Vc = V + (size_t)c0 * stride;
+        if (cn <= 8)
+            hipLaunchKernelGGL(k_multidot<8>, dim3(kRedBlocks), dim3(256), 0, s, Vc, stride, cn, w, len, partial);
+        else if (cn <= 16)
+            hipLaunchKernelGGL(k_multidot<16>, dim3(kRedBlocks), dim3(256), 0, s, Vc, stride, cn, w, len, partial);
+        else
+            hipLaunchKernelGGL(k_multidot<kVec>, dim3(kRedBlocks), dim3(256), 0, s, Vc, stride, cn, w, len, partial);
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, cn, kVec, out + c0);
     }
     return hipGetLastError();
@@ -358,6 +402,7 @@ hipError_t vec_multidot(hipStream_t s, const double* V, size_t stride, int nv, c
 
 hipError_t vec_update(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w, size_t len,
                       double* partial_sq, double* out_sq) {
+    if (stride & 1) return hipErrorInvalidValue;
     for (int c0 = 0; c0 < nv; c0 += kVec) {
         const int cn = std::min(kVec, nv - c0);
         const bool last = c0 + kVec >= nv;
@@ -371,12 +416,16 @@ hipError_t vec_update(hipStream_t s, const double* V, size_t stride, int nv, con
 
 hipError_t vec_update_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w,
                                size_t len, double* partial, double* out) {
-    if (nv > kVec) {  // unfused fallback for long bases
+    if (stride & 1) return hipErrorInvalidValue;
+    if (nv > 16) {  // long bases: separate passes (the fused form would need too many registers)
         hipError_t e = vec_update(s, V, stride, nv, h, w, len, nullptr, nullptr);
         if (e != hipSuccess) return e;
         return vec_multidot(s, V, stride, nv, w, len, partial, out);
     }
-    hipLaunchKernelGGL(k_update_dot, dim3(kRedBlocks), dim3(256), 0, s, V, stride, nv, h, w, len, partial);
+    if (nv <= 8)
+        hipLaunchKernelGGL(k_update_dot<8>, dim3(kRedBlocks), dim3(256), 0, s, V, stride, nv, h, w, len, partial);
+    else
+        hipLaunchKernelGGL(k_update_dot<16>, dim3(kRedBlocks), dim3(256), 0, s, V, stride, nv, h, w, len, partial);
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, nv, kVec, out);
     return hipGetLastError();
 }

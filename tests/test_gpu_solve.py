@@ -114,3 +114,22 @@ def test_restarts_initial_guess_and_errors():
         g.solve(F=Fn, precond="tri")
     assert e.value.code == sgbt.SG_ENAN
     g.close()
+
+
+@pytest.mark.parametrize("m,p,n", [(1, 4, 16), (3, 2, 32), (0, 0, 16)])
+def test_odd_sizes_and_degenerate_chaos(m, p, n):
+    # N*P odd (P = 5, N = 225), a single mode (m = 0: the deterministic problem)
+    import paper_1304_1755_amd as sgbt
+    note(f"solve odd sizes m={m} p={p} n={n}")
+    g = sgbt.Problem(n, m, p, 0.3)
+    o = system.build_problem(n, m, p, 0.3)
+    A = system.assemble_A(o)
+    F = o.rhs().ravel()
+    Ustar = system.solve_direct(o, A=A)
+    for prec in (0, 2):
+        U, info = g.solve(precond="tri", prec=prec, restart=20, rtol=1e-9)
+        Uh = to_host(U).T
+        assert info["status"] == 0
+        assert np.linalg.norm(F - A @ Uh.ravel()) / np.linalg.norm(F) < 1e-9
+        assert rel_max(Uh, Ustar) < 1e-7
+    g.close()
