@@ -46,7 +46,7 @@ int upload_plan(sg_ctx* c, const PlanHost& ph, Plan& pl) {
     pl.W_out = ph.W_out;
     pl.nslot = ph.nslot;
     pl.self = ph.self;
-    for (int s = 0; s < kMaxSlots; ++s) pl.nlist[s] = s < (int)ph.nlist.size() ? ph.nlist[s] : 0;
+    for (int s = 0; s < kMaxSlots; ++s) pl.mask[s] = s < (int)ph.mask.size() ? ph.mask[s] : 0u;
     int rc = upload(c, &pl.d_off, ph.off);
     if (rc) return rc;
     return upload(c, &pl.d_coef, ph.coef);

@@ -45,23 +45,23 @@ struct HostSetup {
 int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_amp, HostSetup& hs);
 
 // coupling tables of one apply "plan": output modes [out_lo, out_lo+W_out),
-// input modes [in_lo, in_lo+W_in).  For each output lane: a list of up to 2m
-// partners, LDS element indices packed two per word (entry 2j low 16 bits,
-// 2j+1 high 16 bits) and their coefficients G_k(alpha, beta); nlist[s] is the
-// longest list among the lanes of slot s.
+// input modes [in_lo, in_lo+W_in).  For each output lane and k: the LDS
+// element indices of the partners alpha + e_k (low 16 bits) and alpha - e_k
+// (high 16 bits) and their coefficients G_k(alpha, beta) at positions 2k and
+// 2k+1; mask[s] marks the positions used by any lane of slot s.
 struct PlanHost {
     int in_lo = 0, W_in = 0, out_lo = 0, W_out = 0, nslot = 1;
     int self = 0;  // include the k = 0 (G_0 = I) term
     std::vector<uint32_t> off;   // nslot*64*m
     std::vector<double> coef;    // nslot*64*2m
-    std::vector<int> nlist;      // nslot
+    std::vector<uint32_t> mask;  // nslot
 };
 PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_out, bool self, bool up, bool down);
 
 // ---------------------------------------------------------------- device side
 struct Plan {
     int in_lo, W_in, out_lo, W_out, nslot, self;
-    int nlist[kMaxSlots];
+    uint32_t mask[kMaxSlots];
     uint32_t* d_off;
     double* d_coef;
 };

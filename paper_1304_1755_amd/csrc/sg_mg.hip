@@ -31,6 +31,15 @@ Tile tile_for(int width) {
     return {tx, 256 / tx};
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Mapping block b to a contiguous range of node chunks per XCD keeps a
+// node's stencil neighbours (the rows above and below) in the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, i = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + i;
+}
+
 template <typename T>
 __global__ void k_fill(T* __restrict__ dst, int ld, int rows, int width) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
@@ -60,7 +69,7 @@ template <typename T, bool WAVE_NODE>
 __global__ void k_gs(const T* __restrict__ sten, T* __restrict__ u, int ldu, const T* __restrict__ f, int ldf,
                      T* __restrict__ out, int ldo, int nx, int width, int rb, int q, int nxc, int nyc, int first) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
-    int t = blockIdx.x * blockDim.y + threadIdx.y;
+    int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
     if (WAVE_NODE) t = __builtin_amdgcn_readfirstlane(t);  // one node per wavefront: scalar stencil loads
     if (mode >= width || t >= nxc * nyc) return;
     const int j = t / nxc, i = t - j * nxc;
@@ -104,7 +113,7 @@ template <typename T>
 __global__ void k_copy_colour(const T* __restrict__ src, int lds, T* __restrict__ u, int ldu, int nx, int width,
                               int q, int nxc, int nyc) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
-    const int t = blockIdx.x * blockDim.y + threadIdx.y;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
     if (mode >= width || t >= nxc * nyc) return;
     const int y = t / nxc, i = t - y * nxc;
     const int x = ((q + y) & 1) + 2 * i;
@@ -113,11 +122,12 @@ __global__ void k_copy_colour(const T* __restrict__ src, int lds, T* __restrict_
     u[node * ldu + mode] = src[node * lds + mode];
 }
 
-template <typename T>
+template <typename T, bool WAVE_NODE>
 __global__ void k_residual(const T* __restrict__ sten, const T* __restrict__ u, int ldu, const T* __restrict__ f,
                            int ldf, T* __restrict__ r, int ldr, int nx, int width) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
-    const int node = blockIdx.x * blockDim.y + threadIdx.y;
+    int node = xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
+    if (WAVE_NODE) node = __builtin_amdgcn_readfirstlane(node);  // one node per wavefront
     if (mode >= width || node >= nx * nx) return;
     const int y = node / nx, x = node - y * nx;
     const T* st = sten + (size_t)node * 9;
@@ -140,7 +150,7 @@ __global__ void k_residual(const T* __restrict__ sten, const T* __restrict__ u, 
 template <typename T>
 __global__ void k_restrict(const T* __restrict__ r, int ldr, T* __restrict__ fc, int ldc, int nxc, int width) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
-    const int node = blockIdx.x * blockDim.y + threadIdx.y;
+    const int node = xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
     if (mode >= width || node >= nxc * nxc) return;
     const int Y = node / nxc, X = node - Y * nxc;
     const int nxf = 2 * nxc + 1;
@@ -158,10 +168,11 @@ __global__ void k_restrict(const T* __restrict__ r, int ldr, T* __restrict__ fc,
     fc[(size_t)node * ldc + mode] = acc;
 }
 
-template <typename T>
+template <typename T, bool WAVE_NODE>
 __global__ void k_prolong_add(const T* __restrict__ ec, int ldc, T* __restrict__ u, int ldu, int nxf, int width) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
-    const int node = blockIdx.x * blockDim.y + threadIdx.y;
+    int node = xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
+    if (WAVE_NODE) node = __builtin_amdgcn_readfirstlane(node);  // one node per wavefront
     if (mode >= width || node >= nxf * nxf) return;
     const int y = node / nxf, x = node - y * nxf;
     const int nxc = (nxf - 1) / 2;
@@ -452,8 +463,12 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
                                width);
         for (int s = 0; s < c->opt.nu1; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, false, tl, s == 0);
         T* r = LevelPtr<T>::r(lv);
-        hipLaunchKernelGGL(k_residual<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                           LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), r, width, lv.nx, width);
+        if (tl.tx == 64)
+            hipLaunchKernelGGL((k_residual<T, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                               LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), r, width, lv.nx, width);
+        else
+            hipLaunchKernelGGL((k_residual<T, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                               LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), r, width, lv.nx, width);
         Level& lc = c->levels[l + 1];
         hipLaunchKernelGGL(k_restrict<T>, grid2(lc.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
                            (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width);
@@ -486,8 +501,12 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     for (int l = Ltop - 1; l >= 0; --l) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
-        hipLaunchKernelGGL(k_prolong_add<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                           (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width);
+        if (tl.tx == 64)
+            hipLaunchKernelGGL((k_prolong_add<T, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width);
+        else
+            hipLaunchKernelGGL((k_prolong_add<T, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width);
         for (int s = 0; s < c->opt.nu2; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, tl, false);
     }
     return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;

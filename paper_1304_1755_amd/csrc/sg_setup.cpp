@@ -300,12 +300,13 @@ int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_a
 }
 
 PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_out, bool self, bool up, bool down) {
-    // Compact partner lists: for every output lane the existing couplings
-    // alpha +- e_k (inside the input range) as (LDS element k*lanes + beta,
-    // G_k(alpha, beta)), ordered by direction (up first) and then k, padded
-    // with the shared zero entry.  A wave reads only as many entries as its
-    // longest list (nlist), which skips the absent partners of the top
-    // degree level and of modes with alpha_k = 0.
+    // Fixed positions per lane: entry 2k is the partner alpha + e_k, entry
+    // 2k+1 the partner alpha - e_k, each as (LDS element k*lanes + beta,
+    // G_k(alpha, beta)), or the shared zero entry when absent.  Keeping the
+    // positions aligned across lanes keeps the gathers close to contiguous.
+    // mask[s] has bit i set when some lane of slot s has entry i, so a wave
+    // skips positions that are empty for all its lanes (e.g. the up partners
+    // of the top degree level).
     PlanHost pl;
     pl.in_lo = in_lo;
     pl.W_in = W_in;
@@ -318,35 +319,29 @@ PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_o
     const uint32_t zero = (uint32_t)(m * lanes);
     pl.off.assign((size_t)lanes * (L / 2), zero | (zero << 16));
     pl.coef.assign((size_t)lanes * L, 0.0);
-    pl.nlist.assign(pl.nslot, 0);
+    pl.mask.assign(pl.nslot, 0u);
     std::map<std::vector<int>, int> pos;
     for (int a = 0; a < hs.P; ++a)
         pos[std::vector<int>(hs.midx.begin() + (size_t)a * m, hs.midx.begin() + (size_t)(a + 1) * m)] = a;
     for (int t = 0; t < W_out; ++t) {
         const int a = out_lo + t;
         std::vector<int> al(hs.midx.begin() + (size_t)a * m, hs.midx.begin() + (size_t)(a + 1) * m);
-        std::vector<std::pair<uint32_t, double>> ent;
-        for (int dir = 0; dir < 2; ++dir) {
-            if ((dir == 0 && !up) || (dir == 1 && !down)) continue;
-            for (int k = 0; k < m; ++k) {
-                if (dir == 1 && al[k] == 0) continue;
+        for (int k = 0; k < m; ++k)
+            for (int dir = 0; dir < 2; ++dir) {
+                if ((dir == 0 && !up) || (dir == 1 && (!down || al[k] == 0))) continue;
                 auto b = al;
                 b[k] += dir == 0 ? 1 : -1;
                 auto it = pos.find(b);
                 if (it == pos.end() || it->second < in_lo || it->second >= in_lo + W_in) continue;
                 // E[xi q_a q_{a+1}] = b_{a+1}: up partner uses a = alpha_k, down partner a = alpha_k - 1
                 const double g = dir == 0 ? legendre_b(al[k] + 1) : legendre_b(al[k]);
-                ent.push_back({(uint32_t)(k * lanes + (it->second - in_lo)), g});
+                const uint32_t idx = (uint32_t)(k * lanes + (it->second - in_lo));
+                uint32_t& w = pl.off[(size_t)t * (L / 2) + k];
+                if (dir == 0) w = (w & 0xFFFF0000u) | idx;
+                else w = (w & 0x0000FFFFu) | (idx << 16);
+                pl.coef[(size_t)t * L + 2 * k + dir] = g;
+                pl.mask[t / 64] |= 1u << (2 * k + dir);
             }
-        }
-        for (size_t i = 0; i < ent.size(); ++i) {
-            uint32_t& w = pl.off[(size_t)t * (L / 2) + i / 2];
-            if (i % 2 == 0) w = (w & 0xFFFF0000u) | ent[i].first;
-            else w = (w & 0x0000FFFFu) | (ent[i].first << 16);
-            pl.coef[(size_t)t * L + i] = ent[i].second;
-        }
-        int& nl = pl.nlist[t / 64];
-        nl = std::max(nl, (int)ent.size());
     }
     return pl;
 }

@@ -313,8 +313,9 @@ __global__ void __launch_bounds__(256) k_grad_cells(const double* __restrict__ U
     if (lane == 0) T[4 * LANES] = 0.0;
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __asm__ __volatile__("" ::: "memory");
-    // partner lists of the full coupling plan: entry i of lane a is the LDS
-    // element k*lanes + b of a partner b = a +- e_k with coefficient G_k(a, b)
+    // coupling tables of the full plan: entry 2k / 2k+1 of lane a is the LDS
+    // element k*lanes + b of the partner b = a + e_k / a - e_k (or the zero
+    // entry), with coefficient G_k(a, b)
     const uint32_t zero = (uint32_t)(m * LANES);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
