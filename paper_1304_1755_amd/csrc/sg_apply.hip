@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(NS * 64)
 k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int ldr,
            Tout* __restrict__ Y, int ldy, const double* __restrict__ cell,
            const uint32_t* __restrict__ toff, const double* __restrict__ tcoef, int n, int W_in,
-           int W_out, int self, int seg, int nseg, uint4 masks) {
+           int W_out, int self, int seg, int nseg) {
     constexpr int MM = M > 0 ? M : 1;
     constexpr int LANES = NS * 64;
     constexpr int BUF = MM * LANES + 2;
@@ -72,7 +72,6 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     const bool vin = t < W_in, vout = t < W_out;
 
     // this lane's partners: position 2k = alpha + e_k, 2k+1 = alpha - e_k
-    const uint32_t used = s == 0 ? masks.x : s == 1 ? masks.y : s == 2 ? masks.z : masks.w;  // uniform
     uint32_t off[MM];
     double ce[2 * MM];
 #pragma unroll
@@ -129,8 +128,10 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
             double acc = self ? s0 : 0.0;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                if (used & (1u << (2 * j))) acc = fma(ce[2 * j], B[off[j] & 0xFFFFu], acc);
-                if (used & (2u << (2 * j))) acc = fma(ce[2 * j + 1], B[off[j] >> 16], acc);
+                // absent partners read the shared zero entry: unconditional
+                // gathers schedule better than skipping positions per wave
+                acc = fma(ce[2 * j], B[off[j] & 0xFFFFu], acc);
+                acc = fma(ce[2 * j + 1], B[off[j] >> 16], acc);
             }
             if (vout) {
                 const size_t node = (size_t)y * nx + x;
@@ -155,7 +156,7 @@ hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, cons
     const int blocks = nx * nseg;
     hipLaunchKernelGGL((k_sg_apply<M, NS, Tin, Tout>), dim3(blocks), dim3(NS * 64), 0, st,
                        (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out, pl.self,
-                       seg, nseg, make_uint4(pl.mask[0], pl.mask[1], pl.mask[2], pl.mask[3]));
+                       seg, nseg);
     return hipGetLastError();
 }
 

@@ -71,8 +71,8 @@ struct Level {
     double* sten64;        // N x 9
     float* sten32;
     // work buffers, capacity N x P
-    double* u64; double* f64; double* r64;
-    float* u32; float* f32; float* r32;
+    double* u64; double* f64; double* r64; double* w64;  // w: second smoothing buffer
+    float* u32; float* f32; float* r32; float* w32;
 };
 
 struct Workspace {

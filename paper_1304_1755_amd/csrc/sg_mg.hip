@@ -210,6 +210,97 @@ __global__ void k_coarse(const double* __restrict__ kinv, const T* __restrict__ 
     }
 }
 
+// ----------------------------------------------------------------- row-phase Gauss-Seidel
+// Four-colour Gauss-Seidel visits, in a forward sweep, the rows with odd y
+// (grid index J even) and then the rows with even y; inside a row it updates
+// first the nodes with x parity fx ("F") and then the others ("S").  The F
+// nodes of a row only need old values of their row and the (stable) rows
+// above and below, and the S nodes need the new F values of their row.  So
+// one launch per row parity updates both colours: a workgroup walks a row
+// segment, computing F(x+1) and then S(x), with the new F values kept in
+// registers and the boundary F values recomputed.  Reads come from A (the
+// sweep's input: own rows) and V (the neighbour rows: A in the first phase,
+// B in the second), writes go to B, so no workgroup reads what another one
+// writes.  One wavefront per 64 modes; lanes are modes.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, const T* __restrict__ A, int lda,
+                                                 const T* __restrict__ V, int ldv, const T* __restrict__ f, int ldf,
+                                                 T* __restrict__ B, int ldb, int nx, int width, int py, int fx,
+                                                 int own_zero, int vert_zero, int seg, int nseg, int nrows) {
+    const int lane = threadIdx.x & 63;
+    const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = s * 64 + lane;
+    const bool ok = t < width;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    if (lb >= nrows * nseg) return;
+    const int r = lb / nseg;
+    const int y = py + 2 * r;
+    const int x0 = (lb - r * nseg) * seg;  // seg is even, so x0 is even
+    const int x1 = min(x0 + seg, nx);
+    const bool has_dn = y > 0 && !vert_zero, has_up = y + 1 < nx && !vert_zero;
+    auto ldA = [&](int x) -> T { return (!own_zero && x >= 0 && x < nx && ok) ? A[((size_t)y * nx + x) * lda + t] : T(0); };
+    auto ldV = [&](int yy, bool has, int x) -> T {
+        return (has && x >= 0 && x < nx && ok) ? V[((size_t)yy * nx + x) * ldv + t] : T(0);
+    };
+    auto ldf_ = [&](int x) -> T { return ok ? f[((size_t)y * nx + x) * ldf + t] : T(0); };
+    // new value at node x of this row from its same-row neighbours wl, wr and
+    // the rows below (d[0..2]) and above (u[0..2]) at x-1, x, x+1
+    auto relax = [&](int x, T wl, T wr, const T* d, const T* up) -> T {
+        const T* st = sten + ((size_t)y * nx + x) * 9;
+        T acc = ldf_(x);
+        acc -= st[0] * d[0] + st[1] * d[1] + st[2] * d[2];
+        acc -= st[6] * up[0] + st[7] * up[1] + st[8] * up[2];
+        acc -= st[3] * wl + st[5] * wr;
+        return acc / st[4];
+    };
+    // first S node at or before x0 whose right F neighbour is x0 or beyond
+    int xs = ((x0 & 1) != fx) ? x0 : x0 - 1;
+    // neighbour-row window at columns xs-1 .. xs+2
+    T dn[4], upr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        dn[i] = ldV(y - 1, has_dn, xs - 1 + i);
+        upr[i] = ldV(y + 1, has_up, xs - 1 + i);
+    }
+    T Sold = ldA(xs);           // old S(xs)
+    // new F(xs - 1) (left of the first S node): recomputed, never written here
+    T Fprev = T(0);
+    if (xs - 1 >= 0) {
+        T d3[3] = {ldV(y - 1, has_dn, xs - 2), dn[0], dn[1]};
+        T u3[3] = {ldV(y + 1, has_up, xs - 2), upr[0], upr[1]};
+        Fprev = relax(xs - 1, ldA(xs - 2), Sold, d3, u3);
+    }
+    for (int x = xs; x < x1; x += 2) {
+        // F(x+1): old S(x), old S(x+2)
+        const T Snext = ldA(x + 2);
+        T Fnew = T(0);
+        if (x + 1 < nx) {
+            const T d3[3] = {dn[1], dn[2], dn[3]};
+            const T u3[3] = {upr[1], upr[2], upr[3]};
+            Fnew = relax(x + 1, Sold, Snext, d3, u3);
+            if (x + 1 >= x0 && x + 1 < x1 && ok) B[((size_t)y * nx + x + 1) * ldb + t] = Fnew;
+        }
+        // S(x): new F(x-1), new F(x+1)
+        if (x >= x0) {
+            const T d3[3] = {dn[0], dn[1], dn[2]};
+            const T u3[3] = {upr[0], upr[1], upr[2]};
+            const T Snew = relax(x, Fprev, Fnew, d3, u3);
+            if (ok) B[((size_t)y * nx + x) * ldb + t] = Snew;
+        }
+        // slide by two columns
+        dn[0] = dn[2];
+        dn[1] = dn[3];
+        upr[0] = upr[2];
+        upr[1] = upr[3];
+        dn[2] = ldV(y - 1, has_dn, x + 3);
+        dn[3] = ldV(y - 1, has_dn, x + 4);
+        upr[2] = ldV(y + 1, has_up, x + 3);
+        upr[3] = ldV(y + 1, has_up, x + 4);
+        Sold = Snext;
+        Fprev = Fnew;
+    }
+}
+
 // ----------------------------------------------------------------- coarse grids in LDS
 // The grids at and below kFusedNx interior nodes per side are cycled by a
 // single launch: one workgroup per right-hand-side column keeps u and f of
@@ -392,6 +483,7 @@ template <typename T>
 struct LevelPtr;
 template <>
 struct LevelPtr<double> {
+    static double* u2(Level& l) { return l.w64; }
     static double* u(Level& l) { return l.u64; }
     static double* f(Level& l) { return l.f64; }
     static double* r(Level& l) { return l.r64; }
@@ -399,6 +491,7 @@ struct LevelPtr<double> {
 };
 template <>
 struct LevelPtr<float> {
+    static float* u2(Level& l) { return l.w32; }
     static float* u(Level& l) { return l.u32; }
     static float* f(Level& l) { return l.f32; }
     static float* r(Level& l) { return l.r32; }
@@ -441,6 +534,52 @@ void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, boo
     }
 }
 
+// nu four-colour sweeps by row phases with ping-pong between u and the
+// level's second buffer; returns with the result in u.  zero_start: u holds
+// the zero initial guess (not read).
+template <typename T>
+void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, bool reverse, int nu,
+                bool zero_start) {
+    Level& lv = c->levels[l];
+    const int nx = lv.nx;
+    T* alt = LevelPtr<T>::u2(lv);
+    const int lda_alt = width;
+    const int seg = 32, nseg = (nx + seg - 1) / seg;
+    const int nws = (width + 63) / 64;
+    T* src = u;
+    int lds = ldu;
+    T* dst = alt;
+    int ldd = lda_alt;
+    for (int sw = 0; sw < nu; ++sw) {
+        const bool own_zero = zero_start && sw == 0;
+        // forward: rows y odd (fx = 1), then y even (fx = 1); backward: y even (fx = 0), then y odd (fx = 0)
+        const int py1 = reverse ? 0 : 1, fx = reverse ? 0 : 1;
+        for (int ph = 0; ph < 2; ++ph) {
+            const int py = ph == 0 ? py1 : 1 - py1;
+            const int nrows = (nx - py + 1) / 2;
+            const T* vsrc = ph == 0 ? src : dst;
+            const int ldv = ph == 0 ? lds : ldd;
+            const int vzero = (ph == 0 && own_zero) ? 1 : 0;
+            hipLaunchKernelGGL(k_gs_rows<T>, dim3(nrows * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv),
+                               (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py, fx, own_zero ? 1 : 0,
+                               vzero, seg, nseg, nrows);
+        }
+        std::swap(src, dst);
+        std::swap(lds, ldd);
+    }
+    if (src != u) {
+        // odd number of sweeps: the result is in the second buffer
+        const Tile tl = tile_for(width);
+        hipLaunchKernelGGL((k_cast<T, T>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream, (const T*)src,
+                           lds, u, ldu, lv.N, width);
+    }
+}
+
+template <typename T>
+bool use_row_sweeps(const sg_ctx* c, int width) {
+    return c->opt.colour_mode == SG_COLOUR_FOUR && width >= 32;
+}
+
 template <typename T>
 int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     const Tile tl = tile_for(width);
@@ -461,7 +600,10 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
         if (c->opt.nu1 == 0)
             hipLaunchKernelGGL(k_fill<T>, grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream, u, uld(l), lv.N,
                                width);
-        for (int s = 0; s < c->opt.nu1; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, false, tl, s == 0);
+        if (use_row_sweeps<T>(c, width))
+            row_sweeps<T>(c, l, u, uld(l), fptr(l), fld(l), width, false, c->opt.nu1, true);
+        else
+            for (int s = 0; s < c->opt.nu1; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, false, tl, s == 0);
         T* r = LevelPtr<T>::r(lv);
         if (tl.tx == 64)
             hipLaunchKernelGGL((k_residual<T, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
@@ -507,7 +649,10 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
         else
             hipLaunchKernelGGL((k_prolong_add<T, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
                                (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width);
-        for (int s = 0; s < c->opt.nu2; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, tl, false);
+        if (use_row_sweeps<T>(c, width))
+            row_sweeps<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, c->opt.nu2, false);
+        else
+            for (int s = 0; s < c->opt.nu2; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, tl, false);
     }
     return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
 }

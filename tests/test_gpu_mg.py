@@ -21,14 +21,18 @@ pytestmark = pytest.mark.gpu
     (128, 20, "rb", (1, 1), 8, False),
     (32, 6, "four", (2, 2), 32, False),
     (16, 1, "rb", (2, 1), 4, True),
+    (256, 126, "four", (2, 2), 8, True),     # row-phase smoother, two waves per node
+    (128, 64, "four", (1, 3), 8, False),     # odd sweep counts (ping-pong ends in the second buffer)
+    (256, 210, "four", (2, 2), 8, False),    # all P modes at once (B_D width)
 ])
 def test_vcycle_matches_oracle(n, width, colour, nu, coarsest, a0):
     import paper_1304_1755_amd as sgbt
     note(f"vcycle n={n} width={width} {colour} {nu} coarsest={coarsest}")
     a0n = sg_inputs.a0_noise_field(n) if a0 else None
-    # m = 4, p = 3 gives P = 35 >= width (the V-cycle work space holds up to P columns)
-    g = sgbt.Problem(n, 4, 3, 0.3, a0_nodal=a0n, colour=colour, nu1=nu[0], nu2=nu[1], coarsest=coarsest)
-    o = system.build_problem(n, 4, 3, 0.3, a0_nodal=a0n)
+    # the V-cycle work space holds up to P columns: m = 4, p = 3 (P = 35) or m = 6, p = 4 (P = 210)
+    m, p = (4, 3) if width <= 35 else (6, 4)
+    g = sgbt.Problem(n, m, p, 0.3, a0_nodal=a0n, colour=colour, nu1=nu[0], nu2=nu[1], coarsest=coarsest)
+    o = system.build_problem(n, m, p, 0.3, a0_nodal=a0n)
     H = mg.Hierarchy(o.K[0], n, coarsest=coarsest, colour_mode=colour, nu1=nu[0], nu2=nu[1])
     f = sg_inputs.uniform_block(g.N, width, seed=11)
     ref = H.vcycle(f)
