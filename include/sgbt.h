@@ -68,8 +68,11 @@ typedef struct {
 } sg_options;
 
 typedef struct {
-    int solver;   /* 0: right-preconditioned FGMRES(restart); 1: PCG (needs precond 0 and prec SG_F64) */
-    int precond;  /* 0: block-diagonal B_D (Sec. 4.1); 1: block-triangular B_T (Sec. 4.2) */
+    int solver;   /* 0: right-preconditioned FGMRES(restart); 1: PCG (precond 0 or 2);
+                     2: GPCG[1] (one stored direction); 3: block Gauss-Seidel iteration
+                     x <- x + B^{-1}(F - A x).  Solvers 1-3 need prec SG_F64. */
+    int precond;  /* 0: block-diagonal B_D (Sec. 4.1); 1: block-triangular B_T (Sec. 4.2);
+                     2: block symmetric Gauss-Seidel B_S (Sec. 4.2) */
     int prec;     /* SG_F64: double V-cycles; SG_MIXED: float V-cycles, double Krylov and residuals */
     int restart;  /* FGMRES restart length, 1..64 */
     int max_it;   /* maximum total iterations */
@@ -139,6 +142,13 @@ int sg_precond_diag(sg_ctx* ctx, const void* R, void* Z, int prec);
 /* Z = B_T^{-1} R: forward block Gauss-Seidel sweep over degree levels with
  * one V-cycle per diagonal block (Sec. 4.2).  Precisions as sg_precond_diag. */
 int sg_precond_tri(sg_ctx* ctx, const void* R, void* Z, int prec);
+
+/* Z = B_S^{-1} R, the block symmetric Gauss-Seidel preconditioner (Sec. 4.2):
+ * the forward sweep of sg_precond_tri, then the backward sweep
+ * Z_d <- Z_d - V-cycle(sum_k [G_k]_{d,d+1} (x) K_k Z_{d+1}) for d = p-1 .. 0.
+ * Symmetric positive definite for double V-cycles (used with PCG).
+ * Precisions as sg_precond_diag. */
+int sg_precond_sym(sg_ctx* ctx, const void* R, void* Z, int prec);
 
 /* Solve A U = F (Sec. 4.2 with Sec. 6 stopping rule).  F, U: device doubles
  * (U holds x0 if opts->use_x0).  info: host, may be NULL.  Returns SG_OK,

@@ -1,4 +1,4 @@
-"""Krylov solvers (oracle; test infrastructure only).
+"""Krylov solvers and the block Gauss-Seidel iteration (oracle; test infrastructure only).
 
 Sec. 4.2: B_T is nonsymmetric, so it is used with GMRes (Saad-Schultz);
 B_D is SPD and used with CG.  Sec. 6: zero initial guess and a stop on the
@@ -11,6 +11,14 @@ still yields x = x0 + Z y; the Arnoldi basis is built by modified
 Gram-Schmidt, the small least-squares problem by Givens rotations, and the
 stop test is the true residual ||F - A x|| / ||F|| recomputed whenever the
 recurrence estimate falls below the tolerance or a cycle ends.
+
+Sec. 4.2 also names GPCG (Blaheta) for the nonsymmetric B_T with the
+symmetric A; GPCG[1] keeps one previous direction: the new direction is the
+preconditioned residual A-orthogonalised against the last direction only,
+p_{k+1} = z_{k+1} - ((A p_k, z_{k+1}) / (A p_k, p_k)) p_k, with
+alpha_k = (r_k, p_k) / (A p_k, p_k).  For a symmetric preconditioner these
+are the conjugate gradient iterates.  Sec. 6 (Table 3) also reports the block
+Gauss-Seidel iteration x_{k+1} = x_k + B_T^{-1}(F - A x_k) (Sec. 4.2).
 """
 
 import numpy as np
@@ -116,4 +124,57 @@ def pcg(A, F, M, tol=1e-8, max_it=1000, x0=None):
         rz_new = np.dot(r, z)
         pvec = z + (rz_new / rz) * pvec
         rz = rz_new
+    return x, info
+
+
+def gpcg1(A, F, M, tol=1e-8, max_it=1000, x0=None):
+    """Generalised preconditioned CG with one stored direction (GPCG[1])."""
+    F = np.asarray(F, dtype=np.float64).ravel()
+    nF = np.linalg.norm(F)
+    x = np.zeros_like(F) if x0 is None else np.asarray(x0, dtype=np.float64).ravel().copy()
+    info = dict(iters=0, est=[], true=[], converged=False)
+    r = F - A(x)
+    if np.linalg.norm(r) / nF < tol:
+        info["converged"] = True
+        return x, info
+    pvec = M(r)
+    while info["iters"] < max_it:
+        q = A(pvec)
+        pq = np.dot(pvec, q)
+        alpha = np.dot(r, pvec) / pq
+        x = x + alpha * pvec
+        r = r - alpha * q
+        info["iters"] += 1
+        rel = np.linalg.norm(r) / nF
+        info["est"].append(rel)
+        if rel < tol:
+            rt = np.linalg.norm(F - A(x)) / nF
+            info["true"].append(rt)
+            if rt < tol:
+                info["converged"] = True
+                break
+        z = M(r)
+        pvec = z - (np.dot(q, z) / pq) * pvec
+    return x, info
+
+
+def block_gs(A, F, M, tol=1e-8, max_it=1000, x0=None):
+    """Stationary iteration x <- x + M(F - A x) (block Gauss-Seidel when M = B_T^{-1})."""
+    F = np.asarray(F, dtype=np.float64).ravel()
+    nF = np.linalg.norm(F)
+    x = np.zeros_like(F) if x0 is None else np.asarray(x0, dtype=np.float64).ravel().copy()
+    info = dict(iters=0, est=[], true=[], converged=False)
+    r = F - A(x)
+    while info["iters"] < max_it:
+        rel = np.linalg.norm(r) / nF
+        info["true"].append(rel)
+        if rel < tol:
+            info["converged"] = True
+            break
+        x = x + M(r)
+        r = F - A(x)
+        info["iters"] += 1
+    else:
+        info["true"].append(np.linalg.norm(r) / nF)
+        info["converged"] = info["true"][-1] < tol
     return x, info

@@ -1,4 +1,4 @@
-"""Block preconditioners B_D and B_T (oracle; test infrastructure only).
+"""Block preconditioners B_D, B_T and B_S (oracle; test infrastructure only).
 
 Sec. 4.1: B_D = G_0 (x) K_0 (one K_0 solve per mode).
 Sec. 4.2: B_T is the lower block-triangular part of A, i.e. one block
@@ -8,6 +8,13 @@ applied recursively down to degree 0), and every diagonal block is
 I (x) K_0 because G_k(alpha, alpha) = 0 for k >= 1; each diagonal solve is
 exact or one V-cycle.  Because the G_k (k >= 1) vanish inside a degree level,
 this equals the mode-by-mode lower block-triangular part of A.
+
+Sec. 4.2 (last display): B_S = B_L blockdiag^{-1} B_U, the block symmetric
+Gauss-Seidel preconditioner for PCG.  With the level-wise reading, B_S^{-1} r
+is a forward sweep y_d = inner(r_d - L_{d,d-1} y_{d-1}) followed by a backward
+sweep z_d = y_d - inner(U_{d,d+1} z_{d+1}) (z_p = y_p), where L and U are the
+strictly lower and upper block parts of A by degree level (U = L^T).  With
+exact inner solves this is (D + U)^{-1} D (D + L)^{-1}.
 
 Arrays are mode-major (P, N), as in ``system``.
 """
@@ -57,6 +64,30 @@ def precond_tri(prob, R, inner):
                     rhs -= Gb @ (prob.K[k] @ Z[prev].T).T
         Z[cur] = apply_block_inverse(inner, rhs)
     return Z
+
+
+def precond_sym(prob, R, inner):
+    """Z = B_S^{-1} R: the forward level sweep of precond_tri, then the backward sweep."""
+    Y = precond_tri(prob, R, inner)
+    Z = Y.copy()
+    off = prob.offsets
+    for d in range(prob.p - 1, -1, -1):
+        cur = slice(off[d], off[d + 1])
+        nxt = slice(off[d + 1], off[d + 2])
+        t = np.zeros((off[d + 1] - off[d], prob.N))
+        for k in range(1, prob.m + 1):
+            Gb = prob.G[k][cur, nxt]
+            if Gb.nnz:
+                t += Gb @ (prob.K[k] @ Z[nxt].T).T
+        Z[cur] = Y[cur] - apply_block_inverse(inner, t)
+    return Z
+
+
+def assemble_BS(prob):
+    """(D + L) D^{-1} (D + U) with D = I (x) K_0 and L, U the strict block parts by level."""
+    BL = assemble_BT(prob)
+    BD = assemble_BD(prob).tocsc()
+    return (BL @ spla.spsolve(BD, BL.T.tocsc())).tocsr()
 
 
 def degree_of_mode(prob):

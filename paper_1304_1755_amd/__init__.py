@@ -23,7 +23,7 @@ SG_F64, SG_F32, SG_MIXED = 0, 1, 2
 SG_COLOUR_FOUR, SG_COLOUR_RB = 0, 1
 
 EXPORTED = ["sg_setup", "sg_query", "sg_get_cell_coeffs", "sg_rhs", "sg_apply", "sg_residual", "sg_vcycle",
-            "sg_precond_diag", "sg_precond_tri", "sg_solve", "sg_qoi", "sg_qoi_grad", "sg_setup_host", "sg_sync",
+            "sg_precond_diag", "sg_precond_tri", "sg_precond_sym", "sg_solve", "sg_qoi", "sg_qoi_grad", "sg_setup_host", "sg_sync",
             "sg_destroy", "sg_last_error"]
 
 
@@ -76,6 +76,7 @@ def load_library():
         "sg_vcycle": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "sg_precond_diag": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "sg_precond_tri": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
+        "sg_precond_sym": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "sg_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
         "sg_qoi": (ctypes.c_int, [vp, vp, dp, dp]),
         "sg_qoi_grad": (ctypes.c_int, [vp, vp, ctypes.POINTER(SolveOpts), dp, dp, dp, dp,
@@ -113,7 +114,8 @@ def _dptr(arr):
 
 def solve_options(solver="fgmres", precond="tri", prec=SG_F64, restart=30, max_it=500, rtol=1e-8,
                   use_x0=False, timing=False):
-    return SolveOpts(solver={"fgmres": 0, "pcg": 1}[solver], precond={"diag": 0, "tri": 1}[precond], prec=prec,
+    return SolveOpts(solver={"fgmres": 0, "pcg": 1, "gpcg": 2, "bgs": 3}[solver],
+                     precond={"diag": 0, "tri": 1, "sym": 2}[precond], prec=prec,
                      restart=restart, max_it=max_it, rtol=rtol, use_x0=int(use_x0), timing=int(timing))
 
 
@@ -224,7 +226,8 @@ class Problem:
     def precond(self, R, Z=None, kind="tri", prec=SG_F64):
         dz = torch.float32 if prec == SG_MIXED else torch.float64
         Z = self.empty(dz) if Z is None else Z
-        fn = load_library().sg_precond_tri if kind == "tri" else load_library().sg_precond_diag
+        lib = load_library()
+        fn = {"tri": lib.sg_precond_tri, "diag": lib.sg_precond_diag, "sym": lib.sg_precond_sym}[kind]
         _check(fn(self._ctx, self._t(R, torch.float64, (self.N, self.P)), self._t(Z, dz, (self.N, self.P)), prec))
         return Z
 

@@ -166,7 +166,34 @@ int precond_tri(sg_ctx* c, const double* R, void* Z, int zf) {
     return SG_OK;
 }
 
+// Z = B_S^{-1} R: the forward sweep, then for d = p-1 .. 0
+// Z_d <- Z_d - V-cycle(sum_k [G_k]_{d,d+1} (x) K_k Z_{d+1}).
+int precond_sym(sg_ctx* c, const double* R, void* Z, int zf) {
+    const int P = c->hs.P, N = c->hs.N, p = c->hs.p;
+    const auto& off = c->hs.offsets;
+    int rc = precond_tri(c, R, Z, zf);
+    if (rc) return rc;
+    if (!c->ws.ustage) {
+        double* q = nullptr;
+        if ((rc = dalloc(c, &q, NP(c)))) return rc;
+        c->ws.ustage = q;
+    }
+    const size_t es = zf ? sizeof(float) : sizeof(double);
+    for (int d = p - 1; d >= 0; --d) {
+        const int lo = off[d], Pd = off[d + 1] - off[d];
+        if (Pd == 0 || off[d + 2] == off[d + 1]) continue;
+        const Plan& pl = c->plan_up[d];
+        const char* zin = (const char*)Z + (size_t)pl.in_lo * es;
+        if ((rc = launch_apply(c, pl, zin, zf, nullptr, c->ws.fstage, zf, P, Pd, P))) return rc;
+        if ((rc = launch_vcycle(c, c->ws.fstage, Pd, c->ws.ustage, Pd, Pd, zf))) return rc;
+        if ((rc = launch_axpy_cols(c->stream, c->ws.ustage, zf, Pd, (char*)Z + (size_t)lo * es, P, N, Pd, -1.0)))
+            return rc;
+    }
+    return SG_OK;
+}
+
 int apply_precond(sg_ctx* c, int kind, const double* R, void* Z, int zf) {
+    if (kind == 2) return precond_sym(c, R, Z, zf);
     return kind == 1 ? precond_tri(c, R, Z, zf) : precond_diag(c, R, Z, zf);
 }
 
@@ -390,13 +417,120 @@ int pcg(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_solve_
     return SG_ENOTCONV;
 }
 
+// GPCG[1]: p_0 = M r_0; alpha = (r, p)/(A p, p); p <- M r - ((A p, M r)/(A p, p)) p
+int gpcg1(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_solve_info& info, Timer& tm) {
+    const size_t np = NP(c);
+    int rc = ensure_scalars(c);
+    if (rc) return rc;
+    if (!c->ws.pcg && (rc = dalloc(c, &c->ws.pcg, 4 * np))) return rc;
+    double *r = c->ws.pcg, *z = r + np, *p = z + np, *q = p + np;
+    double* scal = c->ws.scal;
+    double* hs = c->ws.host_scal;
+    SG_HIP_CHECK(vec_dot(c->stream, F, F, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    const double nF = std::sqrt(hs[0]);
+    if (nF == 0.0) return launch_fill(c->stream, X, 0, 1, (int)np, 1);
+    if (!o.use_x0 && (rc = launch_fill(c->stream, X, 0, 1, (int)np, 1))) return rc;
+    if ((rc = launch_apply(c, c->plan_full, X, 0, F, r, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+    SG_HIP_CHECK(vec_dot(c->stream, r, r, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    info.rel_res_true = std::sqrt(hs[0]) / nF;
+    if (info.rel_res_true < o.rtol) return SG_OK;
+    tm.rec(0, c->stream);
+    if ((rc = apply_precond(c, o.precond, r, p, 0))) return rc;
+    tm.rec(1, c->stream);
+    while (info.iters < o.max_it) {
+        tm.rec(2, c->stream);
+        if ((rc = launch_apply(c, c->plan_full, p, 0, nullptr, q, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+        tm.rec(3, c->stream);
+        SG_HIP_CHECK(vec_dot(c->stream, p, q, np, c->ws.partial, scal));
+        SG_HIP_CHECK(vec_dot(c->stream, r, p, np, c->ws.partial, scal + 1));
+        if ((rc = fetch(c, scal, 2))) return rc;
+        tm.collect(info.iters == 0, true, false);
+        const double pq = hs[0], alpha = hs[1] / pq;
+        SG_HIP_CHECK(vec_axpy(c->stream, alpha, p, X, np));
+        SG_HIP_CHECK(vec_axpy_sq(c->stream, -alpha, q, r, np, c->ws.partial, scal));
+        if ((rc = fetch(c, scal, 1))) return rc;
+        info.iters++;
+        const double rel = std::sqrt(hs[0]) / nF;
+        if (!std::isfinite(rel)) {
+            set_error("GPCG residual is not finite");
+            return SG_ENAN;
+        }
+        if (info.n_hist < 1024) info.rel_res_hist[info.n_hist++] = rel;
+        if (rel < o.rtol) {
+            if ((rc = launch_apply(c, c->plan_full, X, 0, F, z, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+            SG_HIP_CHECK(vec_dot(c->stream, z, z, np, c->ws.partial, scal));
+            if ((rc = fetch(c, scal, 1))) return rc;
+            info.rel_res_true = std::sqrt(hs[0]) / nF;
+            if (info.rel_res_true < o.rtol) return SG_OK;
+        }
+        tm.rec(0, c->stream);
+        if ((rc = apply_precond(c, o.precond, r, z, 0))) return rc;
+        tm.rec(1, c->stream);
+        SG_HIP_CHECK(vec_dot(c->stream, q, z, np, c->ws.partial, scal));
+        if ((rc = fetch(c, scal, 1))) return rc;
+        tm.collect(true, false, false);
+        SG_HIP_CHECK(vec_xpby(c->stream, z, -hs[0] / pq, p, np));
+    }
+    if ((rc = launch_apply(c, c->plan_full, X, 0, F, z, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+    SG_HIP_CHECK(vec_dot(c->stream, z, z, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    info.rel_res_true = std::sqrt(hs[0]) / nF;
+    set_error("GPCG reached max_it above the tolerance");
+    return SG_ENOTCONV;
+}
+
+// block Gauss-Seidel iteration x <- x + M(F - A x)
+int block_gs(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_solve_info& info, Timer& tm) {
+    const size_t np = NP(c);
+    int rc = ensure_scalars(c);
+    if (rc) return rc;
+    if (!c->ws.pcg && (rc = dalloc(c, &c->ws.pcg, 4 * np))) return rc;
+    double *r = c->ws.pcg, *z = r + np;
+    double* scal = c->ws.scal;
+    double* hs = c->ws.host_scal;
+    SG_HIP_CHECK(vec_dot(c->stream, F, F, np, c->ws.partial, scal));
+    if ((rc = fetch(c, scal, 1))) return rc;
+    const double nF = std::sqrt(hs[0]);
+    if (nF == 0.0) return launch_fill(c->stream, X, 0, 1, (int)np, 1);
+    if (!o.use_x0 && (rc = launch_fill(c->stream, X, 0, 1, (int)np, 1))) return rc;
+    while (true) {
+        tm.rec(2, c->stream);
+        if ((rc = launch_apply(c, c->plan_full, X, 0, F, r, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+        tm.rec(3, c->stream);
+        SG_HIP_CHECK(vec_dot(c->stream, r, r, np, c->ws.partial, scal));
+        if ((rc = fetch(c, scal, 1))) return rc;
+        tm.collect(false, true, false);
+        const double rel = std::sqrt(hs[0]) / nF;
+        info.rel_res_true = rel;
+        if (!std::isfinite(rel)) {
+            set_error("block Gauss-Seidel residual is not finite");
+            return SG_ENAN;
+        }
+        if (info.n_hist < 1024) info.rel_res_hist[info.n_hist++] = rel;
+        if (rel < o.rtol) return SG_OK;
+        if (info.iters >= o.max_it) break;
+        tm.rec(0, c->stream);
+        if ((rc = apply_precond(c, o.precond, r, z, 0))) return rc;
+        tm.rec(1, c->stream);
+        SG_HIP_CHECK(vec_axpy(c->stream, 1.0, z, X, np));
+        info.iters++;
+    }
+    set_error("block Gauss-Seidel reached max_it above the tolerance");
+    return SG_ENOTCONV;
+}
+
 int check_opts(const sg_ctx* c, const sg_solve_opts* o) {
     if (!o) return SG_EINVAL;
-    if (o->solver != 0 && o->solver != 1) return SG_EINVAL;
-    if (o->precond != 0 && o->precond != 1) return SG_EINVAL;
+    if (o->solver < 0 || o->solver > 3) return SG_EINVAL;
+    if (o->precond < 0 || o->precond > 2) return SG_EINVAL;
     if (o->prec != SG_F64 && o->prec != SG_MIXED) return SG_EINVAL;
     if (o->solver == 0 && (o->restart < 1 || o->restart > kMaxRestart)) return SG_EINVAL;
-    if (o->solver == 1 && (o->precond != 0 || o->prec != SG_F64)) return SG_EINVAL;
+    // PCG needs a symmetric preconditioner (B_D or B_S); the CG-type solvers
+    // and the stationary iteration run in double only
+    if (o->solver == 1 && o->precond == 1) return SG_EINVAL;
+    if (o->solver != 0 && o->prec != SG_F64) return SG_EINVAL;
     if (o->max_it < 1 || !(o->rtol > 0.0)) return SG_EINVAL;
     (void)c;
     return SG_OK;
@@ -480,10 +614,14 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
     }
     if ((rc = upload_plan(c, make_plan(hs, 0, P, 0, P, true, true, true), c->plan_full))) return fail(rc);
     c->plan_down.assign(hs.p + 1, Plan{});
+    c->plan_up.assign(hs.p + 1, Plan{});
     for (int d = 1; d <= hs.p; ++d) {
         const int lo = hs.offsets[d], Pd = hs.offsets[d + 1] - lo;
         const int plo = hs.offsets[d - 1], Pp = hs.offsets[d] - plo;
         if ((rc = upload_plan(c, make_plan(hs, plo, Pp, lo, Pd, false, false, true), c->plan_down[d])))
+            return fail(rc);
+        // level d-1 outputs from level d inputs (upper coupling of the backward sweep)
+        if ((rc = upload_plan(c, make_plan(hs, lo, Pd, plo, Pp, false, true, false), c->plan_up[d - 1])))
             return fail(rc);
     }
     {
@@ -585,6 +723,14 @@ int sg_precond_tri(sg_ctx* c, const void* R, void* Z, int prec) {
     return precond_tri(c, (const double*)R, Z, prec == SG_MIXED);
 }
 
+int sg_precond_sym(sg_ctx* c, const void* R, void* Z, int prec) {
+    if (!c || !R || !Z || (prec != SG_F64 && prec != SG_MIXED)) {
+        set_error("sg_precond_sym: invalid argument");
+        return SG_EINVAL;
+    }
+    return precond_sym(c, (const double*)R, Z, prec == SG_MIXED);
+}
+
 int sg_solve(sg_ctx* c, const double* F, double* U, const sg_solve_opts* opts, sg_solve_info* info_out) {
     if (!c || !F || !U || check_opts(c, opts) != SG_OK) {
         set_error("sg_solve: invalid argument or options");
@@ -595,7 +741,13 @@ int sg_solve(sg_ctx* c, const double* F, double* U, const sg_solve_opts* opts, s
     Timer tm;
     tm.init(opts->timing != 0);
     auto t0 = std::chrono::steady_clock::now();
-    int rc = opts->solver == 0 ? fgmres(c, F, U, *opts, info, tm) : pcg(c, F, U, *opts, info, tm);
+    int rc;
+    switch (opts->solver) {
+        case 0: rc = fgmres(c, F, U, *opts, info, tm); break;
+        case 1: rc = pcg(c, F, U, *opts, info, tm); break;
+        case 2: rc = gpcg1(c, F, U, *opts, info, tm); break;
+        default: rc = block_gs(c, F, U, *opts, info, tm); break;
+    }
     if (hipStreamSynchronize(c->stream) != hipSuccess && rc == SG_OK) {
         set_error("sg_solve: stream synchronisation failed");
         rc = SG_EHIP;

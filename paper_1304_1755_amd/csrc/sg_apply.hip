@@ -22,6 +22,8 @@
 // precomputed index/coefficient tables held in registers.  A 3x3 window of
 // mode vectors slides along the row, so each step loads one new column.
 
+#include <type_traits>
+
 #include "sg_internal.h"
 
 namespace sg {
@@ -85,22 +87,30 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
         S[1][MM * LANES] = 0.0;
     }
 
-    // window w[row][col]: rows y-1, y, y+1; columns x-1, x, x+1
-    double w[3][3];
-    auto load_col = [&](int col, int xc) {
+    // 4-column window w[row][c]: rows y-1, y, y+1.  Step x uses the columns
+    // x-1, x, x+1 held at c = (x-x0) .. (x-x0)+2 (mod 4) and prefetches column
+    // x+2 into the fourth; the walk is unrolled by 4 so the column roles and
+    // the LDS buffer parity are compile-time constants.
+    double w[3][4];
+    const bool in_slot = has_in;
+    auto load_col = [&](int c, int xc) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const int yy = y + r - 1;
-            const bool ok = has_in && (xc >= 0) && (xc < nx) && (yy >= 0) && (yy < nx);
-            w[r][col] = (ok && vin) ? ld_as_double(U + ((size_t)yy * nx + xc) * ldu + t) : 0.0;
+            const bool okc = in_slot && (xc >= 0) && (xc < nx) && (yy >= 0) && (yy < nx);  // uniform
+            const Tin* rowp = U + ((size_t)yy * nx + xc) * ldu;                           // uniform
+            w[r][c] = (okc && vin) ? ld_as_double(rowp + t) : 0.0;
         }
     };
     load_col(0, x0 - 1);
     load_col(1, x0);
+    load_col(2, x0 + 1);
 
-    for (int x = x0; x < x1; ++x) {
-        double* B = S[(x - x0) & 1];
-        load_col(2, x + 1);
+    auto step = [&](auto cstep, int x) {
+        constexpr int c0 = decltype(cstep)::value;  // window column of x-1
+        constexpr int cW = c0 & 3, cC = (c0 + 1) & 3, cE = (c0 + 2) & 3, cN = (c0 + 3) & 3;
+        double* B = S[c0 & 1];
+        load_col(cN, x + 2);  // prefetch for the next step
         double s0 = 0.0;
         if (has_in) {
             // four cells around the node: SW (x, y), SE (x+1, y), NW (x, y+1), NE (x+1, y+1)
@@ -108,11 +118,11 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
             const double* cSE = cSW + (M + 1);
             const double* cNW = cell + ((size_t)(y + 1) * n + x) * (M + 1);
             const double* cNE = cNW + (M + 1);
-            const double uc4 = 4.0 * w[1][1];
-            const double rSW = fma(-2.0, w[0][0], uc4 - (w[0][1] + w[1][0]));
-            const double rSE = fma(-2.0, w[0][2], uc4 - (w[0][1] + w[1][2]));
-            const double rNW = fma(-2.0, w[2][0], uc4 - (w[2][1] + w[1][0]));
-            const double rNE = fma(-2.0, w[2][2], uc4 - (w[2][1] + w[1][2]));
+            const double uc4 = 4.0 * w[1][cC];
+            const double rSW = fma(-2.0, w[0][cW], uc4 - (w[0][cC] + w[1][cW]));
+            const double rSE = fma(-2.0, w[0][cE], uc4 - (w[0][cC] + w[1][cE]));
+            const double rNW = fma(-2.0, w[2][cW], uc4 - (w[2][cC] + w[1][cW]));
+            const double rNE = fma(-2.0, w[2][cE], uc4 - (w[2][cC] + w[1][cE]));
             s0 = fma(cSW[0], rSW, fma(cSE[0], rSE, fma(cNW[0], rNW, cNE[0] * rNE)));
 #pragma unroll
             for (int k = 1; k <= M; ++k)
@@ -139,11 +149,17 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
                 st_from_double(Y + node * ldy + t, acc);
             }
         }
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            w[r][0] = w[r][1];
-            w[r][1] = w[r][2];
-        }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    for (int x = x0; x < x1; x += 4) {
+        // x, x1 are uniform, so every wave of the block meets the same barriers
+        step(I0{}, x);
+        if (x + 1 < x1) step(I1{}, x + 1);
+        if (x + 2 < x1) step(I2{}, x + 2);
+        if (x + 3 < x1) step(I3{}, x + 3);
     }
 }
 

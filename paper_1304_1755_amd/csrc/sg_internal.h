@@ -89,6 +89,7 @@ struct Workspace {
     double* host_scal = nullptr; // pinned mirror
     // preconditioner staging
     void* fstage = nullptr;      // N x P (float or double) right-hand side staging
+    void* ustage = nullptr;      // N x P staging for the backward sweep of B_S
     size_t fstage_bytes = 0;
     // adjoint
     double* lam = nullptr;       // NP
@@ -111,7 +112,8 @@ struct sg_ctx {
     double* kinv = nullptr;     // N_c x N_c
     std::vector<sg::Level> levels;
     sg::Plan plan_full{};
-    std::vector<sg::Plan> plan_down;  // index d = 1..p
+    std::vector<sg::Plan> plan_down;  // index d = 1..p: level d-1 -> level d
+    std::vector<sg::Plan> plan_up;    // index d = 0..p-1: level d+1 -> level d
     sg::Workspace ws;
     std::vector<void*> allocations;
 };
@@ -127,5 +129,8 @@ int launch_vcycle(sg_ctx* c, const void* f, int ldf, void* u, int ldu, int width
 int launch_cast(hipStream_t s, const void* src, int src_float, int lds, void* dst, int dst_float, int ldd,
                 int rows, int width);
 int launch_fill(hipStream_t s, void* dst, int is_float, int ld, int rows, int width);
+// dst[:, 0:width] += a * src[:, 0:width] (both float or both double, row strides lds / ldd)
+int launch_axpy_cols(hipStream_t s, const void* src, int is_float, int lds, void* dst, int ldd, int rows, int width,
+                     double a);
 
 }  // namespace sg

@@ -47,6 +47,14 @@ __global__ void k_fill(T* __restrict__ dst, int ld, int rows, int width) {
     if (mode < width && row < rows) dst[(size_t)row * ld + mode] = T(0);
 }
 
+template <typename T>
+__global__ void k_axpy_cols(const T* __restrict__ src, int lds, T* __restrict__ dst, int ldd, int rows, int width,
+                            T a) {
+    const int mode = blockIdx.y * blockDim.x + threadIdx.x;
+    const int row = blockIdx.x * blockDim.y + threadIdx.y;
+    if (mode < width && row < rows) dst[(size_t)row * ldd + mode] += a * src[(size_t)row * lds + mode];
+}
+
 template <typename Ts, typename Td>
 __global__ void k_cast(const Ts* __restrict__ src, int lds, Td* __restrict__ dst, int ldd, int rows, int width) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
@@ -681,6 +689,18 @@ int launch_cast(hipStream_t s, const void* src, int src_float, int lds, void* ds
     else
         hipLaunchKernelGGL((k_cast<double, double>), grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s,
                            (const double*)src, lds, (double*)dst, ldd, rows, width);
+    return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
+}
+
+int launch_axpy_cols(hipStream_t s, const void* src, int is_float, int lds, void* dst, int ldd, int rows, int width,
+                     double a) {
+    const Tile tl = tile_for(width);
+    if (is_float)
+        hipLaunchKernelGGL(k_axpy_cols<float>, grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s, (const float*)src, lds,
+                           (float*)dst, ldd, rows, width, (float)a);
+    else
+        hipLaunchKernelGGL(k_axpy_cols<double>, grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s, (const double*)src,
+                           lds, (double*)dst, ldd, rows, width, a);
     return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
 }
 

@@ -86,3 +86,53 @@ def test_block_triangular_needs_fewer_iterations_than_block_diagonal():
     _, it_d = krylov.pcg(lambda v: A @ v, F, Md, tol=1e-8)
     assert it_t["converged"] and it_d["converged"]
     assert it_t["iters"] < it_d["iters"]
+
+
+def test_symmetric_block_gs_preconditioner():
+    # B_S (Sec. 4.2): the sweep form equals the assembled (D+L) D^{-1} (D+U) with exact
+    # blocks, is symmetric positive definite, and PCG with it converges
+    import scipy.sparse.linalg as spla
+    pr = system.build_problem(8, 3, 3, 0.4)
+    R = np.random.default_rng(3).standard_normal((pr.P, pr.N))
+    inner = precond.ExactK0(pr.K[0])
+    Z = precond.precond_sym(pr, R, inner)
+    BS = precond.assemble_BS(pr)
+    Zd = spla.spsolve(BS.tocsc(), R.ravel()).reshape(pr.P, pr.N)
+    assert np.max(np.abs(Z - Zd)) < 1e-11 * np.max(np.abs(Zd))
+    Bd = BS.toarray()
+    assert np.max(np.abs(Bd - Bd.T)) < 1e-12 * np.max(np.abs(Bd))
+    assert np.linalg.eigvalsh(0.5 * (Bd + Bd.T)).min() > 0
+    # with V-cycle blocks the operator is still symmetric (symmetric cycle)
+    H = mg.Hierarchy(pr.K[0], pr.n, coarsest=4)
+    Sv = np.stack([precond.precond_sym(pr, e.reshape(pr.P, pr.N), H.vcycle).ravel()
+                   for e in np.eye(pr.P * pr.N)[:: max(1, pr.P * pr.N // 40)]])
+    idx = np.arange(0, pr.P * pr.N, max(1, pr.P * pr.N // 40))
+    sub = Sv[:, idx]
+    assert np.max(np.abs(sub - sub.T)) < 1e-12 * np.max(np.abs(sub))
+
+
+@pytest.mark.parametrize("inner", ["exact", "vcycle"])
+def test_gpcg1_equals_pcg_for_a_symmetric_preconditioner(inner):
+    pr = system.build_problem(16, 3, 3, 0.3)
+    A, M = _operators(pr, inner, kind="diag")
+    F = pr.rhs().ravel()
+    xc, ic = krylov.pcg(lambda v: A @ v, F, M, tol=1e-10)
+    xg, ig = krylov.gpcg1(lambda v: A @ v, F, M, tol=1e-10)
+    assert ic["converged"] and ig["converged"]
+    assert abs(ic["iters"] - ig["iters"]) <= 1
+    n = min(len(ic["est"]), len(ig["est"]))
+    assert np.allclose(ic["est"][:n - 1], ig["est"][:n - 1], rtol=1e-6)
+
+
+def test_gpcg1_and_block_gs_with_bt_converge():
+    pr = system.build_problem(16, 3, 3, 0.4)
+    A, Mt = _operators(pr, "vcycle", "tri")
+    F = pr.rhs().ravel()
+    U = system.solve_direct(pr, A=A).ravel()
+    for solver in (krylov.gpcg1, krylov.block_gs):
+        x, info = solver(lambda v: A @ v, F, Mt, tol=1e-9, max_it=500)
+        assert info["converged"]
+        assert np.linalg.norm(x - U) / np.linalg.norm(U) < 1e-7
+    _, ig = krylov.gpcg1(lambda v: A @ v, F, Mt, tol=1e-9)
+    _, ib = krylov.block_gs(lambda v: A @ v, F, Mt, tol=1e-9, max_it=500)
+    assert ig["iters"] < ib["iters"]   # the Krylov method beats the stationary iteration
