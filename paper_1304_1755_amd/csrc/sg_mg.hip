@@ -309,6 +309,84 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     }
 }
 
+// Row-phase Gauss-Seidel for narrow blocks (W <= 32 modes): the same
+// sweep as k_gs_rows, but a wavefront's lanes cover (row, mode) pairs -- Wp =
+// W rounded up to a power of two modes per row, 64 / Wp rows per wavefront --
+// and the row segments are short, so that narrow blocks still give enough
+// lanes.  Stencil coefficients become per-lane loads (rows differ by lane).
+template <typename T>
+__global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ sten, const T* __restrict__ A, int lda,
+                                                        const T* __restrict__ V, int ldv, const T* __restrict__ f,
+                                                        int ldf, T* __restrict__ B, int ldb, int nx, int width,
+                                                        int wp_log2, int py, int fx, int own_zero, int vert_zero,
+                                                        int seg, int nseg, int nrows) {
+    const int wp = 1 << wp_log2;
+    const int rows_per_block = (int)blockDim.x >> wp_log2;
+    const int mode = threadIdx.x & (wp - 1);
+    const int ri = threadIdx.x >> wp_log2;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    // block -> (segment, group of rows); rows vary fastest so a block's rows share the segment
+    const int ngroups = (nrows + rows_per_block - 1) / rows_per_block;
+    const int sg = lb / ngroups;
+    const int r = (lb - sg * ngroups) * rows_per_block + ri;
+    if (sg >= nseg || r >= nrows || mode >= width) return;  // no barriers below: lanes may leave
+    const int y = py + 2 * r;
+    const int x0 = sg * seg;
+    const int x1 = min(x0 + seg, nx);
+    const bool has_dn = y > 0 && !vert_zero, has_up = y + 1 < nx && !vert_zero;
+    auto ldA = [&](int x) -> T { return (!own_zero && x >= 0 && x < nx) ? A[((size_t)y * nx + x) * lda + mode] : T(0); };
+    auto ldV = [&](int yy, bool has, int x) -> T {
+        return (has && x >= 0 && x < nx) ? V[((size_t)yy * nx + x) * ldv + mode] : T(0);
+    };
+    auto relax = [&](int x, T wl, T wr, const T* d, const T* up) -> T {
+        const T* st = sten + ((size_t)y * nx + x) * 9;
+        T acc = f[((size_t)y * nx + x) * ldf + mode];
+        acc -= st[0] * d[0] + st[1] * d[1] + st[2] * d[2];
+        acc -= st[6] * up[0] + st[7] * up[1] + st[8] * up[2];
+        acc -= st[3] * wl + st[5] * wr;
+        return acc / st[4];
+    };
+    int xs = ((x0 & 1) != fx) ? x0 : x0 - 1;
+    T dn[4], upr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        dn[i] = ldV(y - 1, has_dn, xs - 1 + i);
+        upr[i] = ldV(y + 1, has_up, xs - 1 + i);
+    }
+    T Sold = ldA(xs);
+    T Fprev = T(0);
+    if (xs - 1 >= 0) {
+        T d3[3] = {ldV(y - 1, has_dn, xs - 2), dn[0], dn[1]};
+        T u3[3] = {ldV(y + 1, has_up, xs - 2), upr[0], upr[1]};
+        Fprev = relax(xs - 1, ldA(xs - 2), Sold, d3, u3);
+    }
+    for (int x = xs; x < x1; x += 2) {
+        const T Snext = ldA(x + 2);
+        T Fnew = T(0);
+        if (x + 1 < nx) {
+            const T d3[3] = {dn[1], dn[2], dn[3]};
+            const T u3[3] = {upr[1], upr[2], upr[3]};
+            Fnew = relax(x + 1, Sold, Snext, d3, u3);
+            if (x + 1 >= x0 && x + 1 < x1) B[((size_t)y * nx + x + 1) * ldb + mode] = Fnew;
+        }
+        if (x >= x0) {
+            const T d3[3] = {dn[0], dn[1], dn[2]};
+            const T u3[3] = {upr[0], upr[1], upr[2]};
+            B[((size_t)y * nx + x) * ldb + mode] = relax(x, Fprev, Fnew, d3, u3);
+        }
+        dn[0] = dn[2];
+        dn[1] = dn[3];
+        upr[0] = upr[2];
+        upr[1] = upr[3];
+        dn[2] = ldV(y - 1, has_dn, x + 3);
+        dn[3] = ldV(y - 1, has_dn, x + 4);
+        upr[2] = ldV(y + 1, has_up, x + 3);
+        upr[3] = ldV(y + 1, has_up, x + 4);
+        Sold = Snext;
+        Fprev = Fnew;
+    }
+}
+
 // ----------------------------------------------------------------- coarse grids in LDS
 // The grids at and below kFusedNx interior nodes per side are cycled by a
 // single launch: one workgroup per right-hand-side column keeps u and f of
@@ -483,6 +561,172 @@ __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const d
     }
 }
 
+// Four-colour variant of the fused coarse-grid cycle with the stencils in
+// registers: every colour class of a fused grid has at most as many nodes as
+// the workgroup has threads, so thread t owns the t-th node of every colour.  Its four 9-point stencils are loaded once per visit of a
+// level; every smoothing pass, residual and prolongation then only touches
+// LDS.
+template <typename T>
+struct OwnNodes {
+    int node[4];
+    int x[4], y[4];
+    T st[4][9];
+};
+
+template <typename T>
+__device__ __forceinline__ void own_nodes(const T* __restrict__ sten, int nx, OwnNodes<T>& on) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int px = (q & 1) ^ 1, py = (q >> 1) ^ 1;
+        const int nxc = (nx - px + 1) / 2, nyc = (nx - py + 1) / 2;
+        const int t = threadIdx.x;
+        on.node[q] = -1;
+        if (t < nxc * nyc) {
+            const int j = t / nxc, i = t - j * nxc;
+            on.x[q] = px + 2 * i;
+            on.y[q] = py + 2 * j;
+            on.node[q] = on.y[q] * nx + on.x[q];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) on.st[q][e] = sten[(size_t)on.node[q] * 9 + e];
+        }
+    }
+}
+
+// acc = f - sum over the stencil of u (skipping the centre when skip_c)
+template <typename T>
+__device__ __forceinline__ T stencil_rest(const OwnNodes<T>& on, int q, const T* u, T fval, int nx, bool skip_c) {
+    const int x = on.x[q], y = on.y[q];
+    T acc = fval;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= nx) continue;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (skip_c && dx == 0 && dy == 0) continue;
+            const int xx = x + dx;
+            if (xx < 0 || xx >= nx) continue;
+            acc -= on.st[q][(dy + 1) * 3 + (dx + 1)] * u[yy * nx + xx];
+        }
+    }
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ void own_smooth(const OwnNodes<T>& on, T* u, const T* f, int nx, bool reverse, int nu) {
+    for (int sweep = 0; sweep < nu; ++sweep)
+#pragma unroll
+        for (int qi = 0; qi < 4; ++qi) {
+            const int q = reverse ? 3 - qi : qi;
+            if (on.node[q] >= 0) {
+                const int nd = on.node[q];
+                u[nd] = stencil_rest<T>(on, q, u, f[nd], nx, true) / on.st[q][4];
+            }
+            __syncthreads();
+        }
+}
+
+// NT threads: at least the largest colour class of the top fused grid
+// (32 x 32 for 63 x 63 float grids, 16 x 16 for 31 x 31 double grids)
+template <typename T>
+constexpr int fused4_threads() { return sizeof(T) == 4 ? 1024 : 256; }
+
+template <typename T>
+__global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_fused4(FusedLevels<T> fl, const double* __restrict__ kinv,
+                                                        const T* __restrict__ fin, int ldf, T* __restrict__ uout,
+                                                        int ldu, int nu1, int nu2) {
+    extern __shared__ char smem_raw[];
+    T* lds = (T*)smem_raw;
+    T* r = lds + fl.roff;
+    const int col = blockIdx.x;
+    const int L = fl.nlev - 1;
+    {
+        const int N0 = fl.nx[0] * fl.nx[0];
+        T* f0 = lds + fl.off[0] + N0;
+        for (int i = threadIdx.x; i < N0; i += blockDim.x) f0[i] = fin[(size_t)i * ldf + col];
+    }
+    __syncthreads();
+    OwnNodes<T> on;
+    for (int l = 0; l < L; ++l) {
+        const int nx = fl.nx[l], N = nx * nx;
+        T* u = lds + fl.off[l];
+        T* f = u + N;
+        own_nodes<T>(fl.sten[l], nx, on);
+        for (int i = threadIdx.x; i < N; i += blockDim.x) u[i] = T(0);
+        __syncthreads();
+        own_smooth<T>(on, u, f, nx, false, nu1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (on.node[q] >= 0) r[on.node[q]] = stencil_rest<T>(on, q, u, f[on.node[q]], nx, false);
+        __syncthreads();
+        const int nxc = fl.nx[l + 1], Nc = nxc * nxc;
+        T* fc = lds + fl.off[l + 1] + Nc;
+        for (int node = threadIdx.x; node < Nc; node += blockDim.x) {
+            const int Y = node / nxc, X = node - Y * nxc;
+            const int fx = 2 * X + 1, fy = 2 * Y + 1;
+            T acc = T(0);
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const T wy = dy == 0 ? T(1) : T(0.5);
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const T wx = dx == 0 ? T(1) : T(0.5);
+                    acc += wx * wy * r[(fy + dy) * nx + (fx + dx)];
+                }
+            }
+            fc[node] = acc;
+        }
+        __syncthreads();
+    }
+    {
+        const int nx = fl.nx[L], N = nx * nx;
+        T* u = lds + fl.off[L];
+        const T* f = u + N;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const double* row = kinv + (size_t)i * N;
+            double acc = 0.0;
+            for (int j = 0; j < N; ++j) acc = fma(row[j], (double)f[j], acc);
+            u[i] = (T)acc;
+        }
+        __syncthreads();
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        const int nx = fl.nx[l], N = nx * nx, nxc = fl.nx[l + 1];
+        T* u = lds + fl.off[l];
+        const T* f = u + N;
+        const T* ec = lds + fl.off[l + 1];
+        own_nodes<T>(fl.sten[l], nx, on);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (on.node[q] < 0) continue;
+            const int x = on.x[q], y = on.y[q];
+            int cx0, cx1, cy0, cy1;
+            T wx, wy;
+            if (x & 1) { cx0 = cx1 = (x - 1) >> 1; wx = T(1); } else { cx0 = (x >> 1) - 1; cx1 = x >> 1; wx = T(0.5); }
+            if (y & 1) { cy0 = cy1 = (y - 1) >> 1; wy = T(1); } else { cy0 = (y >> 1) - 1; cy1 = y >> 1; wy = T(0.5); }
+            T acc = T(0);
+            const int ncx = (cx0 == cx1) ? 1 : 2, ncy = (cy0 == cy1) ? 1 : 2;
+            for (int b = 0; b < ncy; ++b) {
+                const int cy = b ? cy1 : cy0;
+                if (cy < 0 || cy >= nxc) continue;
+                for (int a = 0; a < ncx; ++a) {
+                    const int cx = a ? cx1 : cx0;
+                    if (cx < 0 || cx >= nxc) continue;
+                    acc += ec[cy * nxc + cx];
+                }
+            }
+            u[on.node[q]] += wx * wy * acc;
+        }
+        __syncthreads();
+        own_smooth<T>(on, u, f, nx, true, nu2);
+    }
+    {
+        const int N0 = fl.nx[0] * fl.nx[0];
+        const T* u0 = lds + fl.off[0];
+        for (int i = threadIdx.x; i < N0; i += blockDim.x) uout[(size_t)i * ldu + col] = u0[i];
+    }
+}
+
 inline dim3 grid2(int rows, int width, const Tile& tl) {
     return dim3((rows + tl.ty - 1) / tl.ty, (width + tl.tx - 1) / tl.tx);
 }
@@ -553,6 +797,7 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
     T* alt = LevelPtr<T>::u2(lv);
     const int lda_alt = width;
     const int seg = 32, nseg = (nx + seg - 1) / seg;
+    const int seg_n = 8, nseg_n = (nx + seg_n - 1) / seg_n;  // narrow blocks: short segments, more lanes
     const int nws = (width + 63) / 64;
     T* src = u;
     int lds = ldu;
@@ -568,9 +813,19 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
             const T* vsrc = ph == 0 ? src : dst;
             const int ldv = ph == 0 ? lds : ldd;
             const int vzero = (ph == 0 && own_zero) ? 1 : 0;
-            hipLaunchKernelGGL(k_gs_rows<T>, dim3(nrows * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv),
-                               (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py, fx, own_zero ? 1 : 0,
-                               vzero, seg, nseg, nrows);
+            if (width >= 32) {
+                hipLaunchKernelGGL(k_gs_rows<T>, dim3(nrows * nseg), dim3(64 * nws), 0, c->stream,
+                                   LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py,
+                                   fx, own_zero ? 1 : 0, vzero, seg, nseg, nrows);
+            } else {
+                int wl = 0;
+                while ((1 << wl) < width) ++wl;
+                const int rows_per_block = 256 >> wl;
+                const int ngroups = (nrows + rows_per_block - 1) / rows_per_block;
+                hipLaunchKernelGGL(k_gs_rows_narrow<T>, dim3(ngroups * nseg_n), dim3(256), 0, c->stream,
+                                   LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, wl,
+                                   py, fx, own_zero ? 1 : 0, vzero, seg_n, nseg_n, nrows);
+            }
         }
         std::swap(src, dst);
         std::swap(lds, ldd);
@@ -585,7 +840,8 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
 
 template <typename T>
 bool use_row_sweeps(const sg_ctx* c, int width) {
-    return c->opt.colour_mode == SG_COLOUR_FOUR && width >= 32;
+    (void)width;
+    return c->opt.colour_mode == SG_COLOUR_FOUR;
 }
 
 template <typename T>
@@ -640,9 +896,14 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
         }
         fl.roff = off;
         off += c->levels[Lc].N;
-        hipLaunchKernelGGL(k_vcycle_fused<T>, dim3(width), dim3(512), (size_t)off * sizeof(T), c->stream, fl,
-                           (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2,
-                           c->opt.colour_mode == SG_COLOUR_RB ? 1 : 0);
+        if (c->opt.colour_mode == SG_COLOUR_FOUR)
+            hipLaunchKernelGGL(k_vcycle_fused4<T>, dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T),
+                               c->stream, fl,
+                               (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2);
+        else
+            hipLaunchKernelGGL(k_vcycle_fused<T>, dim3(width), dim3(512), (size_t)off * sizeof(T), c->stream, fl,
+                               (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2,
+                               1);
     } else {
         Level& lc = c->levels[L];
         hipLaunchKernelGGL(k_coarse<T>, dim3(width), dim3(256), (size_t)lc.N * sizeof(double), c->stream, c->kinv,

@@ -24,6 +24,9 @@ pytestmark = pytest.mark.gpu
     (256, 126, "four", (2, 2), 8, True),     # row-phase smoother, two waves per node
     (128, 64, "four", (1, 3), 8, False),     # odd sweep counts (ping-pong ends in the second buffer)
     (256, 210, "four", (2, 2), 8, False),    # all P modes at once (B_D width)
+    (128, 6, "four", (2, 2), 8, False),      # narrow row-phase smoother (lanes over rows and modes)
+    (256, 21, "four", (1, 2), 8, True),
+    (256, 1, "four", (2, 2), 8, False),
 ])
 def test_vcycle_matches_oracle(n, width, colour, nu, coarsest, a0):
     import paper_1304_1755_amd as sgbt
