@@ -225,166 +225,192 @@ __global__ void k_coarse(const double* __restrict__ kinv, const T* __restrict__ 
 // nodes of a row only need old values of their row and the (stable) rows
 // above and below, and the S nodes need the new F values of their row.  So
 // one launch per row parity updates both colours: a workgroup walks a row
-// segment, computing F(x+1) and then S(x), with the new F values kept in
-// registers and the boundary F values recomputed.  Reads come from A (the
-// sweep's input: own rows) and V (the neighbour rows: A in the first phase,
-// B in the second), writes go to B, so no workgroup reads what another one
-// writes.  One wavefront per 64 modes; lanes are modes.
+// segment of kRowSeg nodes, S node by S node, computing F(s+1) and then S(s),
+// with the new F values kept in registers and the F node left of the first S
+// node recomputed.  Reads come from A (the sweep's input: own rows) and V
+// (the neighbour rows: A in the first phase, B in the second), writes go to
+// B, so no workgroup reads what another one writes.  One wavefront per 64
+// modes; lanes are modes.
+//
+// The walk is a chain of dependent steps, so the loads of step i + D are
+// issued before step i is computed (a ring of D register slots): every load
+// address is clamped into the grid and the value is replaced by zero where
+// the node lies outside, so the loads carry no branches and stay in flight
+// while earlier steps compute.  The segment's stencils are staged in LDS
+// once per workgroup.
+constexpr int kRowSeg = 32;
+
 template <typename T>
+constexpr int gs_ring() { return sizeof(T) == 4 ? 4 : 3; }
+
+template <typename T, bool OWNZ>
 __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, const T* __restrict__ A, int lda,
                                                  const T* __restrict__ V, int ldv, const T* __restrict__ f, int ldf,
                                                  T* __restrict__ B, int ldb, int nx, int width, int py, int fx,
-                                                 int own_zero, int vert_zero, int seg, int nseg, int nrows) {
+                                                 int vert_zero, int nseg, int nrows) {
+    constexpr int NIT = kRowSeg / 2;          // S nodes per segment
+    constexpr int D = gs_ring<T>();
+    constexpr int SP = sizeof(T) == 4 ? 12 : 10;  // LDS pitch of a staged stencil
+    __shared__ T stl[(kRowSeg + 2) * SP];
     const int lane = threadIdx.x & 63;
-    const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = s * 64 + lane;
+    const int s_w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = s_w * 64 + lane;
     const bool ok = t < width;
+    const int tc = ok ? t : width - 1;  // lanes past the block load a valid column and store nothing
     const int lb = xcd_block(blockIdx.x, gridDim.x);
-    if (lb >= nrows * nseg) return;
+    if (lb >= nrows * nseg) return;     // uniform over the workgroup
     const int r = lb / nseg;
     const int y = py + 2 * r;
-    const int x0 = (lb - r * nseg) * seg;  // seg is even, so x0 is even
-    const int x1 = min(x0 + seg, nx);
+    const int x0 = (lb - r * nseg) * kRowSeg;  // even
+    const int x1 = min(x0 + kRowSeg, nx);
     const bool has_dn = y > 0 && !vert_zero, has_up = y + 1 < nx && !vert_zero;
-    auto ldA = [&](int x) -> T { return (!own_zero && x >= 0 && x < nx && ok) ? A[((size_t)y * nx + x) * lda + t] : T(0); };
-    auto ldV = [&](int yy, bool has, int x) -> T {
-        return (has && x >= 0 && x < nx && ok) ? V[((size_t)yy * nx + x) * ldv + t] : T(0);
-    };
-    auto ldf_ = [&](int x) -> T { return ok ? f[((size_t)y * nx + x) * ldf + t] : T(0); };
-    // new value at node x of this row from its same-row neighbours wl, wr and
-    // the rows below (d[0..2]) and above (u[0..2]) at x-1, x, x+1
-    auto relax = [&](int x, T wl, T wr, const T* d, const T* up) -> T {
-        const T* st = sten + ((size_t)y * nx + x) * 9;
-        T acc = ldf_(x);
-        acc -= st[0] * d[0] + st[1] * d[1] + st[2] * d[2];
-        acc -= st[6] * up[0] + st[7] * up[1] + st[8] * up[2];
+    const int ydn = y > 0 ? y - 1 : y, yup = y + 1 < nx ? y + 1 : y;
+    // stencils of columns x0-1 .. x0+kRowSeg (clamped), column c at stl[c * SP]
+    for (int i = threadIdx.x; i < (kRowSeg + 2) * 9; i += blockDim.x) {
+        const int c = i / 9, e = i - c * 9;
+        const int x = min(max(x0 - 1 + c, 0), nx - 1);
+        stl[c * SP + e] = sten[((size_t)y * nx + x) * 9 + e];
+    }
+    __syncthreads();
+    auto cx = [&](int x) { return min(max(x, 0), nx - 1); };
+    auto inx = [&](int x) { return x >= 0 && x < nx; };
+    auto gA = [&](int x) -> T { return OWNZ ? T(0) : A[((size_t)y * nx + cx(x)) * lda + tc]; };
+    auto gV = [&](int yy, int x) -> T { return V[((size_t)yy * nx + cx(x)) * ldv + tc]; };
+    auto gf = [&](int x) -> T { return f[((size_t)y * nx + cx(x)) * ldf + tc]; };
+    auto zA = [&](T v, int x) -> T { return (!OWNZ && inx(x)) ? v : T(0); };
+    auto zD = [&](T v, int x) -> T { return (has_dn && inx(x)) ? v : T(0); };
+    auto zU = [&](T v, int x) -> T { return (has_up && inx(x)) ? v : T(0); };
+    // new value at column x from its same-row neighbours wl, wr and the rows
+    // below (d0..d2) and above (u0..u2) at x-1, x, x+1
+    auto relax = [&](int x, T fv, T wl, T wr, T d0, T d1, T d2, T u0, T u1, T u2) -> T {
+        const T* st = stl + (x - x0 + 1) * SP;
+        T acc = fv;
+        acc -= st[0] * d0 + st[1] * d1 + st[2] * d2;
+        acc -= st[6] * u0 + st[7] * u1 + st[8] * u2;
         acc -= st[3] * wl + st[5] * wr;
         return acc / st[4];
     };
-    // first S node at or before x0 whose right F neighbour is x0 or beyond
-    int xs = ((x0 & 1) != fx) ? x0 : x0 - 1;
-    // neighbour-row window at columns xs-1 .. xs+2
-    T dn[4], upr[4];
+    const int sf = x0 + (fx ? 0 : 1);  // first S node of the segment (S parity is 1 - fx)
+    // ring slots: step i reads A(s+2), f(s), f(s+1) and the neighbour rows at s+1, s+2
+    T qa[D], qfs[D], qff[D], qd1[D], qd2[D], qu1[D], qu2[D];
+    auto issue = [&](int i, int k) {
+        const int s = sf + 2 * i;
+        qa[k] = gA(s + 2);
+        qfs[k] = gf(s);
+        qff[k] = gf(s + 1);
+        qd1[k] = gV(ydn, s + 1);
+        qd2[k] = gV(ydn, s + 2);
+        qu1[k] = gV(yup, s + 1);
+        qu2[k] = gV(yup, s + 2);
+    };
+    // prologue: window columns sf-2 .. sf, own values at sf-2 and sf, f(sf-1)
+    T dm = gV(ydn, sf - 2), d0 = gV(ydn, sf - 1), d1 = gV(ydn, sf);
+    T um = gV(yup, sf - 2), u0 = gV(yup, sf - 1), u1 = gV(yup, sf);
+    T am = gA(sf - 2), Sold = gA(sf);
+    const T fp = gf(sf - 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        dn[i] = ldV(y - 1, has_dn, xs - 1 + i);
-        upr[i] = ldV(y + 1, has_up, xs - 1 + i);
-    }
-    T Sold = ldA(xs);           // old S(xs)
-    // new F(xs - 1) (left of the first S node): recomputed, never written here
+    for (int k = 0; k < D; ++k) issue(k, k);
+    dm = zD(dm, sf - 2); d0 = zD(d0, sf - 1); d1 = zD(d1, sf);
+    um = zU(um, sf - 2); u0 = zU(u0, sf - 1); u1 = zU(u1, sf);
+    am = zA(am, sf - 2); Sold = zA(Sold, sf);
+    // new F(sf - 1): belongs to this segment when fx = 0, else to the one on the left
     T Fprev = T(0);
-    if (xs - 1 >= 0) {
-        T d3[3] = {ldV(y - 1, has_dn, xs - 2), dn[0], dn[1]};
-        T u3[3] = {ldV(y + 1, has_up, xs - 2), upr[0], upr[1]};
-        Fprev = relax(xs - 1, ldA(xs - 2), Sold, d3, u3);
+    if (sf - 1 >= 0) {
+        Fprev = relax(sf - 1, fp, am, Sold, dm, d0, d1, um, u0, u1);
+        if (!fx && ok) B[((size_t)y * nx + sf - 1) * ldb + t] = Fprev;
     }
-    for (int x = xs; x < x1; x += 2) {
-        // F(x+1): old S(x), old S(x+2)
-        const T Snext = ldA(x + 2);
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int k = i % D;
+        const int s = sf + 2 * i;
+        const T Snext = zA(qa[k], s + 2);
+        const T fS = qfs[k], fF = qff[k];
+        const T d2 = zD(qd1[k], s + 1), d3 = zD(qd2[k], s + 2);
+        const T u2 = zU(qu1[k], s + 1), u3 = zU(qu2[k], s + 2);
+        if (i + D < NIT) issue(i + D, k);
+        // F(s+1) from old S(s), S(s+2); zero outside the grid
         T Fnew = T(0);
-        if (x + 1 < nx) {
-            const T d3[3] = {dn[1], dn[2], dn[3]};
-            const T u3[3] = {upr[1], upr[2], upr[3]};
-            Fnew = relax(x + 1, Sold, Snext, d3, u3);
-            if (x + 1 >= x0 && x + 1 < x1 && ok) B[((size_t)y * nx + x + 1) * ldb + t] = Fnew;
+        if (s + 1 < nx) {
+            Fnew = relax(s + 1, fF, Sold, Snext, d1, d2, d3, u1, u2, u3);
+            if (s + 1 < x1 && ok) B[((size_t)y * nx + s + 1) * ldb + t] = Fnew;
         }
-        // S(x): new F(x-1), new F(x+1)
-        if (x >= x0) {
-            const T d3[3] = {dn[0], dn[1], dn[2]};
-            const T u3[3] = {upr[0], upr[1], upr[2]};
-            const T Snew = relax(x, Fprev, Fnew, d3, u3);
-            if (ok) B[((size_t)y * nx + x) * ldb + t] = Snew;
+        // S(s) from new F(s-1), F(s+1)
+        if (s < x1) {
+            const T Snew = relax(s, fS, Fprev, Fnew, d0, d1, d2, u0, u1, u2);
+            if (ok) B[((size_t)y * nx + s) * ldb + t] = Snew;
         }
-        // slide by two columns
-        dn[0] = dn[2];
-        dn[1] = dn[3];
-        upr[0] = upr[2];
-        upr[1] = upr[3];
-        dn[2] = ldV(y - 1, has_dn, x + 3);
-        dn[3] = ldV(y - 1, has_dn, x + 4);
-        upr[2] = ldV(y + 1, has_up, x + 3);
-        upr[3] = ldV(y + 1, has_up, x + 4);
+        d0 = d2;
+        d1 = d3;
+        u0 = u2;
+        u1 = u3;
         Sold = Snext;
         Fprev = Fnew;
     }
 }
 
-// Row-phase Gauss-Seidel for narrow blocks (W <= 32 modes): the same
-// sweep as k_gs_rows, but a wavefront's lanes cover (row, mode) pairs -- Wp =
-// W rounded up to a power of two modes per row, 64 / Wp rows per wavefront --
-// and the row segments are short, so that narrow blocks still give enough
-// lanes.  Stencil coefficients become per-lane loads (rows differ by lane).
-template <typename T>
+// Row-phase Gauss-Seidel for narrow blocks (W <= 32 modes): the same update
+// as k_gs_rows without the walk.  A lane owns, for one mode, the S node s of
+// a row and the F node s + 1, and recomputes the F node s - 1 that its S
+// update also needs; lanes cover (row, S node, mode) with Wp = W rounded up
+// to a power of two lanes per node, so narrow blocks still fill the chip and
+// every lane issues all its loads at once.  Addresses are clamped into the
+// grid and values outside it replaced by zero.
+template <typename T, bool OWNZ>
 __global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ sten, const T* __restrict__ A, int lda,
                                                         const T* __restrict__ V, int ldv, const T* __restrict__ f,
                                                         int ldf, T* __restrict__ B, int ldb, int nx, int width,
-                                                        int wp_log2, int py, int fx, int own_zero, int vert_zero,
-                                                        int seg, int nseg, int nrows) {
-    const int wp = 1 << wp_log2;
-    const int rows_per_block = (int)blockDim.x >> wp_log2;
-    const int mode = threadIdx.x & (wp - 1);
-    const int ri = threadIdx.x >> wp_log2;
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
-    // block -> (segment, group of rows); rows vary fastest so a block's rows share the segment
-    const int ngroups = (nrows + rows_per_block - 1) / rows_per_block;
-    const int sg = lb / ngroups;
-    const int r = (lb - sg * ngroups) * rows_per_block + ri;
-    if (sg >= nseg || r >= nrows || mode >= width) return;  // no barriers below: lanes may leave
+                                                        int wp_log2, int py, int fx, int vert_zero, int npairs,
+                                                        int nrows) {
+    const int mode = threadIdx.x & ((1 << wp_log2) - 1);
+    const long gl = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const long pl = gl >> wp_log2;
+    const int r = (int)(pl / npairs);
+    const int j = (int)(pl - (long)r * npairs);
+    if (r >= nrows || mode >= width) return;  // no barriers below
     const int y = py + 2 * r;
-    const int x0 = sg * seg;
-    const int x1 = min(x0 + seg, nx);
+    // S nodes have parity 1 - fx; with fx = 0 the first pair is (none, F(0))
+    const int s = 2 * j - (fx ? 0 : 1);
     const bool has_dn = y > 0 && !vert_zero, has_up = y + 1 < nx && !vert_zero;
-    auto ldA = [&](int x) -> T { return (!own_zero && x >= 0 && x < nx) ? A[((size_t)y * nx + x) * lda + mode] : T(0); };
-    auto ldV = [&](int yy, bool has, int x) -> T {
-        return (has && x >= 0 && x < nx) ? V[((size_t)yy * nx + x) * ldv + mode] : T(0);
-    };
-    auto relax = [&](int x, T wl, T wr, const T* d, const T* up) -> T {
-        const T* st = sten + ((size_t)y * nx + x) * 9;
-        T acc = f[((size_t)y * nx + x) * ldf + mode];
-        acc -= st[0] * d[0] + st[1] * d[1] + st[2] * d[2];
-        acc -= st[6] * up[0] + st[7] * up[1] + st[8] * up[2];
-        acc -= st[3] * wl + st[5] * wr;
-        return acc / st[4];
-    };
-    int xs = ((x0 & 1) != fx) ? x0 : x0 - 1;
-    T dn[4], upr[4];
+    const int ydn = y > 0 ? y - 1 : y, yup = y + 1 < nx ? y + 1 : y;
+    auto cx = [&](int x) { return min(max(x, 0), nx - 1); };
+    auto inx = [&](int x) { return x >= 0 && x < nx; };
+    auto gA = [&](int x) -> T { return OWNZ ? T(0) : A[((size_t)y * nx + cx(x)) * lda + mode]; };
+    auto gV = [&](int yy, int x) -> T { return V[((size_t)yy * nx + cx(x)) * ldv + mode]; };
+    auto gf = [&](int x) -> T { return f[((size_t)y * nx + cx(x)) * ldf + mode]; };
+    T a[3], fv[3], dn[5], up[5], st[3][9];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        dn[i] = ldV(y - 1, has_dn, xs - 1 + i);
-        upr[i] = ldV(y + 1, has_up, xs - 1 + i);
+    for (int i = 0; i < 3; ++i) {
+        a[i] = gA(s - 2 + 2 * i);
+        fv[i] = gf(s - 1 + i);
+        const T* sp = sten + ((size_t)y * nx + cx(s - 1 + i)) * 9;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) st[i][e] = sp[e];
     }
-    T Sold = ldA(xs);
-    T Fprev = T(0);
-    if (xs - 1 >= 0) {
-        T d3[3] = {ldV(y - 1, has_dn, xs - 2), dn[0], dn[1]};
-        T u3[3] = {ldV(y + 1, has_up, xs - 2), upr[0], upr[1]};
-        Fprev = relax(xs - 1, ldA(xs - 2), Sold, d3, u3);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        dn[i] = gV(ydn, s - 2 + i);
+        up[i] = gV(yup, s - 2 + i);
     }
-    for (int x = xs; x < x1; x += 2) {
-        const T Snext = ldA(x + 2);
-        T Fnew = T(0);
-        if (x + 1 < nx) {
-            const T d3[3] = {dn[1], dn[2], dn[3]};
-            const T u3[3] = {upr[1], upr[2], upr[3]};
-            Fnew = relax(x + 1, Sold, Snext, d3, u3);
-            if (x + 1 >= x0 && x + 1 < x1) B[((size_t)y * nx + x + 1) * ldb + mode] = Fnew;
-        }
-        if (x >= x0) {
-            const T d3[3] = {dn[0], dn[1], dn[2]};
-            const T u3[3] = {upr[0], upr[1], upr[2]};
-            B[((size_t)y * nx + x) * ldb + mode] = relax(x, Fprev, Fnew, d3, u3);
-        }
-        dn[0] = dn[2];
-        dn[1] = dn[3];
-        upr[0] = upr[2];
-        upr[1] = upr[3];
-        dn[2] = ldV(y - 1, has_dn, x + 3);
-        dn[3] = ldV(y - 1, has_dn, x + 4);
-        upr[2] = ldV(y + 1, has_up, x + 3);
-        upr[3] = ldV(y + 1, has_up, x + 4);
-        Sold = Snext;
-        Fprev = Fnew;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a[i] = (!OWNZ && inx(s - 2 + 2 * i)) ? a[i] : T(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        dn[i] = (has_dn && inx(s - 2 + i)) ? dn[i] : T(0);
+        up[i] = (has_up && inx(s - 2 + i)) ? up[i] : T(0);
     }
+    // node s - 1 + i (i = 0, 1, 2) with same-row neighbours wl, wr
+    auto relax = [&](int i, T wl, T wr) -> T {
+        const T* c = st[i];
+        T acc = fv[i];
+        acc -= c[0] * dn[i] + c[1] * dn[i + 1] + c[2] * dn[i + 2];
+        acc -= c[6] * up[i] + c[7] * up[i + 1] + c[8] * up[i + 2];
+        acc -= c[3] * wl + c[5] * wr;
+        return acc / c[4];
+    };
+    const T Fl = inx(s - 1) ? relax(0, a[0], a[1]) : T(0);
+    const T Fr = inx(s + 1) ? relax(2, a[1], a[2]) : T(0);
+    if (inx(s + 1)) B[((size_t)y * nx + s + 1) * ldb + mode] = Fr;
+    if (inx(s)) B[((size_t)y * nx + s) * ldb + mode] = relax(1, Fl, Fr);
 }
 
 // ----------------------------------------------------------------- coarse grids in LDS
@@ -796,8 +822,7 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
     const int nx = lv.nx;
     T* alt = LevelPtr<T>::u2(lv);
     const int lda_alt = width;
-    const int seg = 32, nseg = (nx + seg - 1) / seg;
-    const int seg_n = 8, nseg_n = (nx + seg_n - 1) / seg_n;  // narrow blocks: short segments, more lanes
+    const int nseg = (nx + kRowSeg - 1) / kRowSeg;
     const int nws = (width + 63) / 64;
     T* src = u;
     int lds = ldu;
@@ -814,17 +839,28 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
             const int ldv = ph == 0 ? lds : ldd;
             const int vzero = (ph == 0 && own_zero) ? 1 : 0;
             if (width >= 32) {
-                hipLaunchKernelGGL(k_gs_rows<T>, dim3(nrows * nseg), dim3(64 * nws), 0, c->stream,
-                                   LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py,
-                                   fx, own_zero ? 1 : 0, vzero, seg, nseg, nrows);
+                if (own_zero)
+                    hipLaunchKernelGGL((k_gs_rows<T, true>), dim3(nrows * nseg), dim3(64 * nws), 0, c->stream,
+                                       LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width,
+                                       py, fx, vzero, nseg, nrows);
+                else
+                    hipLaunchKernelGGL((k_gs_rows<T, false>), dim3(nrows * nseg), dim3(64 * nws), 0, c->stream,
+                                       LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width,
+                                       py, fx, vzero, nseg, nrows);
             } else {
                 int wl = 0;
                 while ((1 << wl) < width) ++wl;
-                const int rows_per_block = 256 >> wl;
-                const int ngroups = (nrows + rows_per_block - 1) / rows_per_block;
-                hipLaunchKernelGGL(k_gs_rows_narrow<T>, dim3(ngroups * nseg_n), dim3(256), 0, c->stream,
-                                   LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, wl,
-                                   py, fx, own_zero ? 1 : 0, vzero, seg_n, nseg_n, nrows);
+                const int npairs = fx ? (nx - 1) / 2 + 1 : nx / 2 + 1;  // pairs (S(s), F(s+1)) covering the row
+                const long lanes = (long)nrows * npairs << wl;
+                const int nblk = (int)((lanes + 255) / 256);
+                if (own_zero)
+                    hipLaunchKernelGGL((k_gs_rows_narrow<T, true>), dim3(nblk), dim3(256), 0, c->stream,
+                                       LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width,
+                                       wl, py, fx, vzero, npairs, nrows);
+                else
+                    hipLaunchKernelGGL((k_gs_rows_narrow<T, false>), dim3(nblk), dim3(256), 0, c->stream,
+                                       LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width,
+                                       wl, py, fx, vzero, npairs, nrows);
             }
         }
         std::swap(src, dst);
