@@ -230,6 +230,17 @@ int fetch(sg_ctx* c, const double* dsrc, int count) {
     return SG_OK;
 }
 
+// Right-preconditioned flexible GMRES(restart).  The Arnoldi basis is built
+// by classical Gram-Schmidt with delayed reorthogonalization: in step j the
+// candidate u = V_j left by step j-1 (orthogonalized once, not normalized)
+// is preconditioned as it is (the flexible method accepts any z_j), and one
+// pass of dot products [Q, u]^T [u, w] (w = A z_j) yields both the second
+// orthogonalization of u and the projection of w.  The final q_j then
+// replaces u, and column j-1 of the Hessenberg matrix takes the small
+// correction that the second orthogonalization implies, so A Z = Q H stays
+// exact; the Givens rotations for the running residual estimate use the
+// uncorrected columns, and the least-squares problem at the end of a cycle
+// is solved on the corrected matrix.
 int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_solve_info& info, Timer& tm) {
     const size_t np = NP(c);
     const int restart = o.restart;
@@ -255,9 +266,9 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
         return SG_ENAN;
     }
     if (!o.use_x0 && (rc = launch_fill(c->stream, X, 0, 1, (int)np, 1))) return rc;
-    // r = F - A X
-    if ((rc = launch_apply(c, c->plan_full, X, 0, F, c->ws.w, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
-    SG_HIP_CHECK(vec_dot(c->stream, c->ws.w, c->ws.w, np, c->ws.partial, scal));
+    // r = F - A X, kept unnormalized as the first candidate V_0
+    if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+    SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
     if ((rc = fetch(c, scal, 1))) return rc;
     double beta = std::sqrt(hs[0]);
     info.rel_res_true = beta / nF;
@@ -267,14 +278,18 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
     }
     if (beta / nF < o.rtol) return SG_OK;
 
-    std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
-    auto Hat = [&](int i, int j) -> double& { return H[(size_t)i * restart + j]; };
+    const int ld = restart;
+    // Hc: corrected Hessenberg matrix; Hr: columns as rotated for the running estimate
+    std::vector<double> Hc((size_t)(restart + 1) * ld), Hr((size_t)(restart + 1) * ld), cs(restart), sn(restart),
+        g(restart + 1), y(restart), a(restart), b(restart), cc(restart);
+    auto HC = [&](int i, int j) -> double& { return Hc[(size_t)i * ld + j]; };
+    auto HR = [&](int i, int j) -> double& { return Hr[(size_t)i * ld + j]; };
     while (info.iters < o.max_it) {
-        SG_HIP_CHECK(vec_scale(c->stream, c->ws.w, 1.0 / beta, Vj(0), np));
-        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(Hc.begin(), Hc.end(), 0.0);
+        std::fill(Hr.begin(), Hr.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
-        int jlast = 0;
+        int k = 0;  // columns of this cycle
         for (int j = 0; j < restart; ++j) {
             tm.rec(0, c->stream);
             if ((rc = apply_precond(c, o.precond, Vj(j), Zj(j), zf))) return rc;
@@ -284,55 +299,103 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
                 return rc;
             tm.rec(3, c->stream);
             tm.rec(4, c->stream);
-            // classical Gram-Schmidt, twice; the first update and the second
-            // projection share one pass over the basis
-            SG_HIP_CHECK(vec_multidot(c->stream, c->ws.V, vs, j + 1, c->ws.w, np, c->ws.partial, scal));
-            SG_HIP_CHECK(vec_update_multidot(c->stream, c->ws.V, vs, j + 1, scal, c->ws.w, np, c->ws.partial,
-                                             scal + 128));
-            SG_HIP_CHECK(vec_update(c->stream, c->ws.V, vs, j + 1, scal + 128, c->ws.w, np, c->ws.partial,
-                                    scal + 256));
+            SG_HIP_CHECK(vec_dots2(c->stream, c->ws.V, vs, j, Vj(j), c->ws.w, np, c->ws.partial, scal));
+            const int nch = j == 0 ? 1 : (j + kDc - 1) / kDc;
+            if ((rc = fetch(c, scal, nch * kDcLd))) return rc;
+            for (int i = 0; i < j; ++i) {
+                a[i] = hs[(i / kDc) * kDcLd + (i % kDc)];
+                b[i] = hs[(i / kDc) * kDcLd + kDc + (i % kDc)];
+            }
+            const double uu = hs[2 * kDc], uw = hs[2 * kDc + 1];
+            double nu2 = uu, ab = 0.0;
+            for (int i = 0; i < j; ++i) {
+                nu2 -= a[i] * a[i];
+                ab += a[i] * b[i];
+            }
+            if (!std::isfinite(nu2) || !std::isfinite(uw) || !std::isfinite(ab)) {
+                set_error("Arnoldi vector is not finite");
+                return SG_ENAN;
+            }
+            if (!(nu2 > 0.0)) {
+                // the candidate lies in the span of the basis: breakdown after column j - 1
+                if (j > 0) HC(j, j - 1) = 0.0;
+                break;
+            }
+            const double nu = std::sqrt(nu2);
+            if (j > 0) {  // column j - 1: u = sum_i a_i q_i + nu q_j
+                for (int i = 0; i < j; ++i) HC(i, j - 1) += a[i];
+                HC(j, j - 1) = nu;
+            }
+            const double hjj = (uw - ab) / nu;
+            for (int i = 0; i < j; ++i) {
+                HC(i, j) = b[i];
+                a[i] /= nu;
+                cc[i] = b[i] - hjj * a[i];
+            }
+            HC(j, j) = hjj;
+            // q_j = (u - Q a) / nu into V_j;  w' = w - Q b - hjj q_j into V_{j+1}
+            SG_HIP_CHECK(vec_update2(c->stream, c->ws.V, vs, j, a.data(), cc.data(), 1.0 / nu, hjj / nu, Vj(j),
+                                     c->ws.w, Vj(j + 1), np, c->ws.partial, scal + 256));
             tm.rec(5, c->stream);
-            SG_HIP_CHECK(hipMemcpyAsync(hs, scal, 257 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-            SG_HIP_CHECK(hipStreamSynchronize(c->stream));
+            if ((rc = fetch(c, scal + 256, 1))) return rc;
             tm.collect(true, true, true);
-            for (int i = 0; i <= j; ++i) Hat(i, j) = hs[i] + hs[128 + i];
-            const double hn = std::sqrt(hs[256]);
+            const double hn = std::sqrt(hs[0]);
             if (!std::isfinite(hn)) {
                 set_error("Arnoldi vector norm is not finite");
                 return SG_ENAN;
             }
-            Hat(j + 1, j) = hn;
-            const bool breakdown = hn == 0.0;
-            if (!breakdown) SG_HIP_CHECK(vec_scale(c->stream, c->ws.w, 1.0 / hn, Vj(j + 1), np));
+            HC(j + 1, j) = hn;  // provisional until the next step reorthogonalizes V_{j+1}
+            // running estimate from the uncorrected column
+            for (int i = 0; i <= j + 1; ++i) HR(i, j) = HC(i, j);
             for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
-                Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
-                Hat(i, j) = t;
+                const double t = cs[i] * HR(i, j) + sn[i] * HR(i + 1, j);
+                HR(i + 1, j) = -sn[i] * HR(i, j) + cs[i] * HR(i + 1, j);
+                HR(i, j) = t;
             }
-            const double den = std::hypot(Hat(j, j), Hat(j + 1, j));
-            cs[j] = Hat(j, j) / den;
-            sn[j] = Hat(j + 1, j) / den;
-            Hat(j, j) = den;
-            Hat(j + 1, j) = 0.0;
+            const double den = std::hypot(HR(j, j), HR(j + 1, j));
+            cs[j] = HR(j, j) / den;
+            sn[j] = HR(j + 1, j) / den;
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
             info.iters++;
+            k = j + 1;
             const double est = std::fabs(g[j + 1]) / nF;
             if (info.n_hist < 1024) info.rel_res_hist[info.n_hist++] = est;
-            jlast = j;
-            if (est < o.rtol || breakdown || info.iters >= o.max_it) break;
+            if (est < o.rtol || hn == 0.0 || info.iters >= o.max_it) break;
         }
-        const int k = jlast + 1;
+        if (k == 0) {
+            set_error("FGMRES breakdown in the first step");
+            return SG_ENAN;
+        }
+        // least squares min |beta e_0 - Hc y| by Givens rotations on the corrected columns
+        std::vector<double> R((size_t)(k + 1) * k), gg(k + 1, 0.0);
+        for (int i = 0; i <= k; ++i)
+            for (int jj = 0; jj < k; ++jj) R[(size_t)i * k + jj] = HC(i, jj);
+        gg[0] = beta;
+        for (int jj = 0; jj < k; ++jj) {
+            for (int i = 0; i < jj; ++i) {
+                const double t = cs[i] * R[(size_t)i * k + jj] + sn[i] * R[(size_t)(i + 1) * k + jj];
+                R[(size_t)(i + 1) * k + jj] = -sn[i] * R[(size_t)i * k + jj] + cs[i] * R[(size_t)(i + 1) * k + jj];
+                R[(size_t)i * k + jj] = t;
+            }
+            const double d = std::hypot(R[(size_t)jj * k + jj], R[(size_t)(jj + 1) * k + jj]);
+            cs[jj] = R[(size_t)jj * k + jj] / d;
+            sn[jj] = R[(size_t)(jj + 1) * k + jj] / d;
+            R[(size_t)jj * k + jj] = d;
+            R[(size_t)(jj + 1) * k + jj] = 0.0;
+            gg[jj + 1] = -sn[jj] * gg[jj];
+            gg[jj] = cs[jj] * gg[jj];
+        }
         for (int i = k - 1; i >= 0; --i) {
-            double s = g[i];
-            for (int l = i + 1; l < k; ++l) s -= Hat(i, l) * y[l];
-            y[i] = s / Hat(i, i);
+            double sacc = gg[i];
+            for (int l = i + 1; l < k; ++l) sacc -= R[(size_t)i * k + l] * y[l];
+            y[i] = sacc / R[(size_t)i * k + i];
         }
         std::memcpy(hs + 512, y.data(), k * sizeof(double));
         SG_HIP_CHECK(hipMemcpyAsync(scal + 512, hs + 512, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
         SG_HIP_CHECK(vec_combine(c->stream, c->ws.Z, zf, vs, k, scal + 512, X, np));
-        if ((rc = launch_apply(c, c->plan_full, X, 0, F, c->ws.w, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
-        SG_HIP_CHECK(vec_dot(c->stream, c->ws.w, c->ws.w, np, c->ws.partial, scal));
+        if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+        SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
         if ((rc = fetch(c, scal, 1))) return rc;
         beta = std::sqrt(hs[0]);
         info.rel_res_true = beta / nF;

@@ -10,13 +10,26 @@
 namespace sg {
 
 constexpr int kRedBlocks = 1024;  // fixed reduction grid: deterministic partial sums
+constexpr int kDc = 16;           // basis vectors per orthogonalization pass
+constexpr int kDcLd = 2 * kDc + 2;  // outputs per chunk of vec_dots2
 
-hipError_t vec_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* w, size_t len,
-                        double* partial, double* out);
-hipError_t vec_update(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w, size_t len,
-                      double* partial_sq, double* out_sq);
-hipError_t vec_update_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w,
-                               size_t len, double* partial, double* out);
+// per-chunk coefficients of the orthogonalization update pass (kernel argument)
+struct DcCoef {
+    double a[kDc];
+    double c[kDc];
+    double alpha, gamma;
+};
+
+// Arnoldi passes with delayed reorthogonalization (chunks of kDc basis vectors).
+// vec_dots2: out[34 ch + i] = Q_{16 ch + i} . u, out[34 ch + 16 + i] = Q_{16 ch + i} . w,
+// out[34 ch + 32] = u . u, out[34 ch + 33] = u . w  (ch = 0 .. ceil(nv / 16) - 1).
+hipError_t vec_dots2(hipStream_t s, const double* Q, size_t stride, int nv, const double* u, const double* w,
+                     size_t len, double* partial, double* out);
+// vec_update2: u <- alpha u - sum_i a[i] Q_i, wout <- w - gamma u_old - sum_i c[i] Q_i (host a, c),
+// out_sq = |wout|^2 when partial_sq and out_sq are given.
+hipError_t vec_update2(hipStream_t s, const double* Q, size_t stride, int nv, const double* a, const double* c,
+                       double alpha, double gamma, double* u, const double* w, double* wout, size_t len,
+                       double* partial_sq, double* out_sq);
 hipError_t vec_dot(hipStream_t s, const double* a, const double* b, size_t len, double* partial, double* out);
 hipError_t vec_scale(hipStream_t s, const double* src, double a, double* dst, size_t len);
 hipError_t vec_combine(hipStream_t s, const void* Z, int z_float, size_t stride, int nz, const double* y, double* x,

@@ -31,92 +31,121 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
-constexpr int kVec = 32;  // basis vectors handled by one pass
-
+// Arnoldi orthogonalization by classical Gram-Schmidt with delayed
+// reorthogonalization: the newest basis vector u is orthogonalized a second
+// time in the same two passes that orthogonalize the next candidate w, so
+// each step reads the basis twice (a pass of dot products, then a pass of
+// updates) instead of three times plus a normalization.  Bases longer than
+// kDc vectors are processed in chunks.
+//
 // Basis passes work on pairs of doubles (16-byte loads): the basis stride
 // must be even (the launchers check it); an odd length leaves one last
 // element, handled by one thread.
 
-// partial[b][i] = sum over block b's elements of V_i[e] * w[e], i < nv (nv <= NV)
+// partial[b][i] = sum_e Q_i[e] u[e], partial[b][kDc + i] = sum_e Q_i[e] w[e]
+// (i < nv), partial[b][2 kDc] = u.u, partial[b][2 kDc + 1] = u.w, summed over
+// block b's elements
 template <int NV>
-__global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, size_t stride, int nv,
-                                                  const double* __restrict__ w, size_t len,
-                                                  double* __restrict__ partial) {
+__global__ void __launch_bounds__(256) k_dots2(const double* __restrict__ Q, size_t stride, int nv,
+                                               const double* __restrict__ u, const double* __restrict__ w,
+                                               size_t len, double* __restrict__ partial) {
     __shared__ double sh[4];
-    double acc[NV];
+    double aa[NV], bb[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int i = 0; i < NV; ++i) aa[i] = bb[i] = 0.0;
+    double uu = 0.0, uw = 0.0;
     const size_t half = len / 2;
+    const double2* u2 = (const double2*)u;
     const double2* w2 = (const double2*)w;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < half; e += (size_t)gridDim.x * blockDim.x) {
-        const double2 we = w2[e];
+        const double2 ue = u2[e], we = w2[e];
+        uu = fma(ue.x, ue.x, fma(ue.y, ue.y, uu));
+        uw = fma(ue.x, we.x, fma(ue.y, we.y, uw));
 #pragma unroll
         for (int i = 0; i < NV; ++i)
             if (i < nv) {
-                const double2 vv = ((const double2*)(V + (size_t)i * stride))[e];
-                acc[i] = fma(vv.x, we.x, fma(vv.y, we.y, acc[i]));
+                const double2 q = ((const double2*)(Q + (size_t)i * stride))[e];
+                aa[i] = fma(q.x, ue.x, fma(q.y, ue.y, aa[i]));
+                bb[i] = fma(q.x, we.x, fma(q.y, we.y, bb[i]));
             }
     }
     if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // odd length: last element
+        const double ue = u[len - 1], we = w[len - 1];
+        uu = fma(ue, ue, uu);
+        uw = fma(ue, we, uw);
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) acc[i] = fma(V[(size_t)i * stride + len - 1], w[len - 1], acc[i]);
+            if (i < nv) {
+                const double q = Q[(size_t)i * stride + len - 1];
+                aa[i] = fma(q, ue, aa[i]);
+                bb[i] = fma(q, we, bb[i]);
+            }
     }
+    double* out = partial + (size_t)blockIdx.x * kDcLd;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        if (i < nv) {  // uniform: keeps the loop unrolled and acc[] in registers
-            const double t = block_sum(acc[i], sh);
-            if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kVec + i] = t;
+        if (i < nv) {  // uniform: keeps the loop unrolled and the sums in registers
+            const double ta = block_sum(aa[i], sh);
+            if (threadIdx.x == 0) out[i] = ta;
+            const double tb = block_sum(bb[i], sh);
+            if (threadIdx.x == 0) out[kDc + i] = tb;
         }
     }
+    const double tu = block_sum(uu, sh);
+    if (threadIdx.x == 0) out[2 * kDc] = tu;
+    const double tw = block_sum(uw, sh);
+    if (threadIdx.x == 0) out[2 * kDc + 1] = tw;
 }
 
-// Second Gram-Schmidt pass fused with the first update (short bases, NV <= 16):
-//   w <- w - sum_i h[i] V_i,  partial[b][i] = sum over block b of V_i[e] * w_new[e]
+// Update pass over one chunk of the basis, elementwise:
+//   uout = alpha uin - sum_i cf.a[i] Q_i,   wout = win - gamma uin - sum_i cf.c[i] Q_i
+// and, when partial_sq is given, block partial sums of wout^2.  uout may be
+// uin and wout may be win (each thread reads its elements before writing).
 template <int NV>
-__global__ void __launch_bounds__(256) k_update_dot(const double* __restrict__ V, size_t stride, int nv,
-                                                    const double* __restrict__ h, double* __restrict__ w,
-                                                    size_t len, double* __restrict__ partial) {
+__global__ void __launch_bounds__(256) k_update2(const double* __restrict__ Q, size_t stride, int nv, DcCoef cf,
+                                                 const double* uin, const double* win, double* uout, double* wout,
+                                                 size_t len, double* __restrict__ partial_sq) {
     __shared__ double sh[4];
-    __shared__ double hs[NV];
-    if (threadIdx.x < NV) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
-    __syncthreads();
-    double acc[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    double sq = 0.0;
     const size_t half = len / 2;
-    double2* w2 = (double2*)w;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < half; e += (size_t)gridDim.x * blockDim.x) {
-        double2 v[NV];
-        double2 we = w2[e];
+        const double2 ue = ((const double2*)uin)[e];
+        const double2 we = ((const double2*)win)[e];
+        double2 qn, wn;
+        qn.x = cf.alpha * ue.x;
+        qn.y = cf.alpha * ue.y;
+        wn.x = fma(-cf.gamma, ue.x, we.x);
+        wn.y = fma(-cf.gamma, ue.y, we.y);
 #pragma unroll
         for (int i = 0; i < NV; ++i)
             if (i < nv) {
-                v[i] = ((const double2*)(V + (size_t)i * stride))[e];
-                we.x = fma(-hs[i], v[i].x, we.x);
-                we.y = fma(-hs[i], v[i].y, we.y);
+                const double2 q = ((const double2*)(Q + (size_t)i * stride))[e];
+                qn.x = fma(-cf.a[i], q.x, qn.x);
+                qn.y = fma(-cf.a[i], q.y, qn.y);
+                wn.x = fma(-cf.c[i], q.x, wn.x);
+                wn.y = fma(-cf.c[i], q.y, wn.y);
             }
-        w2[e] = we;
-#pragma unroll
-        for (int i = 0; i < NV; ++i)
-            if (i < nv) acc[i] = fma(v[i].x, we.x, fma(v[i].y, we.y, acc[i]));
+        ((double2*)uout)[e] = qn;
+        ((double2*)wout)[e] = wn;
+        sq = fma(wn.x, wn.x, fma(wn.y, wn.y, sq));
     }
     if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // odd length: last element
-        double we = w[len - 1];
+        const double ue = uin[len - 1], we = win[len - 1];
+        double qn = cf.alpha * ue, wn = fma(-cf.gamma, ue, we);
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) we = fma(-hs[i], V[(size_t)i * stride + len - 1], we);
-        w[len - 1] = we;
-#pragma unroll
-        for (int i = 0; i < NV; ++i)
-            if (i < nv) acc[i] = fma(V[(size_t)i * stride + len - 1], we, acc[i]);
+            if (i < nv) {
+                const double q = Q[(size_t)i * stride + len - 1];
+                qn = fma(-cf.a[i], q, qn);
+                wn = fma(-cf.c[i], q, wn);
+            }
+        uout[len - 1] = qn;
+        wout[len - 1] = wn;
+        sq = fma(wn, wn, sq);
     }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        if (i < nv) {
-            const double t = block_sum(acc[i], sh);
-            if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kVec + i] = t;
-        }
+    if (partial_sq) {
+        const double t = block_sum(sq, sh);
+        if (threadIdx.x == 0) partial_sq[blockIdx.x] = t;
     }
 }
 
@@ -129,43 +158,6 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int nblock
         for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[(size_t)b * ldp + i];
         const double t = block_sum(v, sh);
         if (threadIdx.x == 0) out[i] = t;
-    }
-}
-
-// w -= sum_i h[i] V_i ; optionally partial sums of the new w^2
-__global__ void __launch_bounds__(256) k_update(const double* __restrict__ V, size_t stride, int nv,
-                                                const double* __restrict__ h, double* __restrict__ w, size_t len,
-                                                double* __restrict__ partial_sq) {
-    __shared__ double sh[4];
-    __shared__ double hs[kVec];
-    if (threadIdx.x < kVec) hs[threadIdx.x] = threadIdx.x < nv ? h[threadIdx.x] : 0.0;
-    __syncthreads();
-    double sq = 0.0;
-    const size_t half = len / 2;
-    double2* w2 = (double2*)w;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < half; e += (size_t)gridDim.x * blockDim.x) {
-        double2 we = w2[e];
-#pragma unroll
-        for (int i = 0; i < kVec; ++i)
-            if (i < nv) {
-                const double2 vv = ((const double2*)(V + (size_t)i * stride))[e];
-                we.x = fma(-hs[i], vv.x, we.x);
-                we.y = fma(-hs[i], vv.y, we.y);
-            }
-        w2[e] = we;
-        sq = fma(we.x, we.x, fma(we.y, we.y, sq));
-    }
-    if ((len & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // odd length: last element
-        double we = w[len - 1];
-#pragma unroll
-        for (int i = 0; i < kVec; ++i)
-            if (i < nv) we = fma(-hs[i], V[(size_t)i * stride + len - 1], we);
-        w[len - 1] = we;
-        sq = fma(we, we, sq);
-    }
-    if (partial_sq) {
-        const double t = block_sum(sq, sh);
-        if (threadIdx.x == 0) partial_sq[blockIdx.x] = t;
     }
 }
 
@@ -383,54 +375,51 @@ __global__ void k_grad_a0(const double* __restrict__ dc, int n, int m, double* _
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-hipError_t vec_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* w, size_t len,
-                        double* partial, double* out) {
+hipError_t vec_dots2(hipStream_t s, const double* Q, size_t stride, int nv, const double* u, const double* w,
+                     size_t len, double* partial, double* out) {
     if (stride & 1) return hipErrorInvalidValue;  // pairs of doubles need an even basis stride
-    // nv may exceed kVec: process the basis in chunks
-    for (int c0 = 0; c0 < nv; c0 += kVec) {
-        const int cn = std::min(kVec, nv - c0);
-        const double* Vc = V + (size_t)c0 * stride;
+    const int nch = nv == 0 ? 1 : (nv + kDc - 1) / kDc;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int c0 = ch * kDc, cn = std::min(kDc, nv - c0);
+        const double* Qc = Q + (size_t)c0 * stride;
         if (cn <= 8)
-            hipLaunchKernelGGL(k_multidot<8>, dim3(kRedBlocks), dim3(256), 0, s, Vc, stride, cn, w, len, partial);
-        else if (cn <= 16)
-            hipLaunchKernelGGL(k_multidot<16>, dim3(kRedBlocks), dim3(256), 0, s, Vc, stride, cn, w, len, partial);
+            hipLaunchKernelGGL(k_dots2<8>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, u, w, len, partial);
         else
-            hipLaunchKernelGGL(k_multidot<kVec>, dim3(kRedBlocks), dim3(256), 0, s, Vc, stride, cn, w, len, partial);
-        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, cn, kVec, out + c0);
+            hipLaunchKernelGGL(k_dots2<kDc>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, u, w, len, partial);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, kDcLd, kDcLd,
+                           out + (size_t)ch * kDcLd);
     }
     return hipGetLastError();
 }
-
-hipError_t vec_update(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w, size_t len,
-                      double* partial_sq, double* out_sq) {
+hipError_t vec_update2(hipStream_t s, const double* Q, size_t stride, int nv, const double* a, const double* c,
+                       double alpha, double gamma, double* u, const double* w, double* wout, size_t len,
+                       double* partial_sq, double* out_sq) {
     if (stride & 1) return hipErrorInvalidValue;
-    for (int c0 = 0; c0 < nv; c0 += kVec) {
-        const int cn = std::min(kVec, nv - c0);
-        const bool last = c0 + kVec >= nv;
-        hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, s, V + (size_t)c0 * stride, stride, cn, h + c0,
-                           w, len, (last && partial_sq) ? partial_sq : nullptr);
+    const int nch = nv == 0 ? 1 : (nv + kDc - 1) / kDc;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int c0 = ch * kDc, cn = std::min(kDc, nv - c0);
+        DcCoef cf{};
+        for (int i = 0; i < cn; ++i) {
+            cf.a[i] = a[c0 + i];
+            cf.c[i] = c[c0 + i];
+        }
+        // the first chunk scales u and takes gamma u from w; later chunks continue from the outputs
+        cf.alpha = ch == 0 ? alpha : 1.0;
+        cf.gamma = ch == 0 ? gamma : 0.0;
+        const double* win = ch == 0 ? w : wout;
+        double* psq = ch == nch - 1 ? partial_sq : nullptr;
+        const double* Qc = Q + (size_t)c0 * stride;
+        if (cn <= 8)
+            hipLaunchKernelGGL(k_update2<8>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, cf, (const double*)u,
+                               win, u, wout, len, psq);
+        else
+            hipLaunchKernelGGL(k_update2<kDc>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, cf,
+                               (const double*)u, win, u, wout, len, psq);
     }
     if (partial_sq && out_sq)
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial_sq, kRedBlocks, 1, 1, out_sq);
     return hipGetLastError();
 }
-
-hipError_t vec_update_multidot(hipStream_t s, const double* V, size_t stride, int nv, const double* h, double* w,
-                               size_t len, double* partial, double* out) {
-    if (stride & 1) return hipErrorInvalidValue;
-    if (nv > 16) {  // long bases: separate passes (the fused form would need too many registers)
-        hipError_t e = vec_update(s, V, stride, nv, h, w, len, nullptr, nullptr);
-        if (e != hipSuccess) return e;
-        return vec_multidot(s, V, stride, nv, w, len, partial, out);
-    }
-    if (nv <= 8)
-        hipLaunchKernelGGL(k_update_dot<8>, dim3(kRedBlocks), dim3(256), 0, s, V, stride, nv, h, w, len, partial);
-    else
-        hipLaunchKernelGGL(k_update_dot<16>, dim3(kRedBlocks), dim3(256), 0, s, V, stride, nv, h, w, len, partial);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, nv, kVec, out);
-    return hipGetLastError();
-}
-
 hipError_t vec_dot(hipStream_t s, const double* a, const double* b, size_t len, double* partial, double* out) {
     hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, len, partial);
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, 1, 1, out);
