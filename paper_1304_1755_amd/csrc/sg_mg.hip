@@ -176,6 +176,209 @@ __global__ void k_restrict(const T* __restrict__ r, int ldr, T* __restrict__ fc,
     fc[(size_t)node * ldc + mode] = acc;
 }
 
+// Residual and restriction in one pass for wide blocks (W >= 32 modes):
+// fc = R (f - K u) without storing the fine residual.  A workgroup walks a
+// segment of kRrSeg nodes of one coarse row Y; lanes are modes.  Per coarse
+// column X it forms the row-weighted fine residual c(x) = r(x, fy-1)/2 +
+// r(x, fy) + r(x, fy+1)/2 (fy = 2Y+1) at x = 2X+1 and 2X+2, from a window
+// of five fine rows of u, and then fc(X) = c(2X)/2 + c(2X+1) + c(2X+2)/2.
+// Loads are clamped into the grid (zero outside) and issued a ring of steps
+// ahead; the stencils of the three fine rows are staged in LDS.
+constexpr int kRrSeg = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ sten, const T* __restrict__ u, int ldu,
+                                                        const T* __restrict__ f, int ldf, T* __restrict__ fc,
+                                                        int ldc, int nxc, int width, int nseg) {
+    constexpr int D = 2;
+    constexpr int NC = 2 * kRrSeg + 1;                 // staged fine columns 2 X0 .. 2 X0 + 2 kRrSeg
+    constexpr int SP = sizeof(T) == 4 ? 12 : 10;
+    __shared__ T stl[3 * NC * SP];
+    const int lane = threadIdx.x & 63;
+    const int s_w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = s_w * 64 + lane;
+    const bool ok = t < width;
+    const int tc = ok ? t : width - 1;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    if (lb >= nxc * nseg) return;  // uniform over the workgroup
+    const int Y = lb / nseg;
+    const int X0 = (lb - Y * nseg) * kRrSeg;
+    const int X1 = min(X0 + kRrSeg, nxc);
+    const int nxf = 2 * nxc + 1;
+    const int fy = 2 * Y + 1;
+    const int xb = 2 * X0;  // first fine column of the walk
+    for (int i = threadIdx.x; i < 3 * NC * 9; i += blockDim.x) {
+        const int rk = i / (NC * 9), rem = i - rk * (NC * 9);
+        const int c = rem / 9, e = rem - c * 9;
+        const int x = min(xb + c, nxf - 1);
+        stl[(rk * NC + c) * SP + e] = sten[((size_t)(fy - 1 + rk) * nxf + x) * 9 + e];
+    }
+    __syncthreads();
+    // fine rows fy-2 .. fy+2 of u (k = 0..4): only the outer two can leave the grid
+    const bool rv0 = fy - 2 >= 0, rv4 = fy + 2 < nxf;
+    auto cx = [&](int x) { return min(max(x, 0), nxf - 1); };
+    auto inx = [&](int x) { return x >= 0 && x < nxf; };
+    auto gu = [&](int k, int x) -> T {
+        const int yy = min(max(fy - 2 + k, 0), nxf - 1);
+        return u[((size_t)yy * nxf + cx(x)) * ldu + tc];
+    };
+    auto gf = [&](int k, int x) -> T { return f[((size_t)(fy - 1 + k) * nxf + x) * ldf + tc]; };
+    auto zu = [&](T v, int k, int x) -> T {
+        const bool rv = k == 0 ? rv0 : (k == 4 ? rv4 : true);
+        return (rv && inx(x)) ? v : T(0);
+    };
+    // c(x) from u columns x-1, x, x+1 (U[k][0..2]) and f at rows fy-1..fy+1
+    auto colres = [&](int x, const T (*U)[3], const T* fv) -> T {
+        T r3[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T* st = stl + (k * NC + (x - xb)) * SP;
+            T acc = fv[k];
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) acc -= st[dy * 3 + dx] * U[k + dy][dx];
+            r3[k] = acc;
+        }
+        return T(0.5) * r3[0] + r3[1] + T(0.5) * r3[2];
+    };
+    // ring slots: step i (X = X0 + i) loads u columns 2X+2, 2X+3 and f columns 2X+1, 2X+2
+    T qu2[D][5], qu3[D][5], qf1[D][3], qf2[D][3];
+    auto issue = [&](int i, int s) {
+        const int x = 2 * (X0 + i);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            qu2[s][k] = gu(k, x + 2);
+            qu3[s][k] = gu(k, x + 3);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            qf1[s][k] = gf(k, min(x + 1, nxf - 1));
+            qf2[s][k] = gf(k, min(x + 2, nxf - 1));
+        }
+    };
+    // prologue: u columns xb-1, xb, xb+1 and f at xb give c(xb)
+    T W[5][3], f0[3];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        W[k][0] = gu(k, xb - 1);
+        W[k][1] = gu(k, xb);
+        W[k][2] = gu(k, xb + 1);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f0[k] = gf(k, xb);
+#pragma unroll
+    for (int s = 0; s < D; ++s) issue(s, s);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        W[k][0] = zu(W[k][0], k, xb - 1);
+        W[k][1] = zu(W[k][1], k, xb);
+        W[k][2] = zu(W[k][2], k, xb + 1);
+    }
+    T cprev = colres(xb, W, f0);
+#pragma unroll
+    for (int i = 0; i < kRrSeg; ++i) {
+        const int s = i % D;
+        const int X = X0 + i;
+        const int x = 2 * X;
+        // window for column x+1: u columns x, x+1, x+2
+        T A[5][3], Bw[5][3], fa[3], fb[3];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const T u2 = zu(qu2[s][k], k, x + 2), u3 = zu(qu3[s][k], k, x + 3);
+            A[k][0] = W[k][1];
+            A[k][1] = W[k][2];
+            A[k][2] = u2;
+            Bw[k][0] = W[k][2];
+            Bw[k][1] = u2;
+            Bw[k][2] = u3;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            fa[k] = qf1[s][k];
+            fb[k] = qf2[s][k];
+        }
+        if (i + D < kRrSeg) issue(i + D, s);
+        if (X < X1) {
+            const T c1 = colres(x + 1, A, fa);
+            const T c2 = colres(x + 2, Bw, fb);
+            if (ok) fc[((size_t)Y * nxc + X) * ldc + t] = T(0.5) * cprev + c1 + T(0.5) * c2;
+            cprev = c2;
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            W[k][1] = Bw[k][1];
+            W[k][2] = Bw[k][2];
+        }
+    }
+}
+
+// Bilinear prolongation added to u for wide blocks (W >= 32 modes): a
+// workgroup walks kPrSeg nodes of one fine row; lanes are modes.  The fine
+// row takes the coarse row it lies on (odd y) or the mean of the two it lies
+// between (even y); along the row, odd x takes the coarse value it lies on
+// and even x the mean of its two neighbours.  Loads are clamped (zero
+// outside the coarse grid) and issued a ring of steps ahead.
+constexpr int kPrSeg = 32;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong_rows(const T* __restrict__ ec, int ldc, T* __restrict__ u, int ldu,
+                                                      int nxf, int width, int nseg) {
+    constexpr int D = 4;
+    constexpr int NIT = kPrSeg / 2;
+    const int lane = threadIdx.x & 63;
+    const int s_w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = s_w * 64 + lane;
+    const bool ok = t < width;
+    const int tc = ok ? t : width - 1;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    if (lb >= nxf * nseg) return;
+    const int y = lb / nseg;
+    const int x0 = (lb - y * nseg) * kPrSeg;  // even
+    const int x1 = min(x0 + kPrSeg, nxf);
+    const int nxc = (nxf - 1) / 2;
+    int ya, yb;
+    T wy;
+    if (y & 1) { ya = yb = (y - 1) >> 1; wy = T(1); }
+    else { ya = (y >> 1) - 1; yb = y >> 1; wy = T(0.5); }
+    const bool va_ok = ya >= 0, vb_ok = (y & 1) ? false : yb < nxc;
+    const int yac = max(ya, 0), ybc = min(yb, nxc - 1);
+    auto cX = [&](int X) { return min(max(X, 0), nxc - 1); };
+    auto gca = [&](int X) -> T { return ec[((size_t)yac * nxc + cX(X)) * ldc + tc]; };
+    auto gcb = [&](int X) -> T { return ec[((size_t)ybc * nxc + cX(X)) * ldc + tc]; };
+    auto erow = [&](T a, T b, int X) -> T {
+        if (X < 0 || X >= nxc) return T(0);
+        const T av = va_ok ? a : T(0), bv = vb_ok ? b : T(0);
+        return (y & 1) ? av : wy * (av + bv);
+    };
+    auto gu = [&](int x) -> T { return u[((size_t)y * nxf + min(x, nxf - 1)) * ldu + tc]; };
+    const int Xs = x0 >> 1;  // step i covers fine columns 2(Xs+i), 2(Xs+i)+1
+    T qa[D], qb[D], q0[D], q1[D];
+    auto issue = [&](int i, int s) {
+        const int X = Xs + i;
+        qa[s] = gca(X);
+        qb[s] = gcb(X);
+        q0[s] = gu(2 * X);
+        q1[s] = gu(2 * X + 1);
+    };
+    T pa = gca(Xs - 1), pb = gcb(Xs - 1);
+#pragma unroll
+    for (int s = 0; s < D; ++s) issue(s, s);
+    T eprev = erow(pa, pb, Xs - 1);
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int s = i % D;
+        const int X = Xs + i;
+        const T e = erow(qa[s], qb[s], X);
+        const T u0 = q0[s], u1 = q1[s];
+        if (i + D < NIT) issue(i + D, s);
+        const int xe = 2 * X, xo = 2 * X + 1;
+        if (ok && xe < x1) u[((size_t)y * nxf + xe) * ldu + t] = u0 + T(0.5) * (eprev + e);
+        if (ok && xo < x1) u[((size_t)y * nxf + xo) * ldu + t] = u1 + e;
+        eprev = e;
+    }
+}
+
 template <typename T, bool WAVE_NODE>
 __global__ void k_prolong_add(const T* __restrict__ ec, int ldc, T* __restrict__ u, int ldu, int nxf, int width) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
@@ -904,16 +1107,23 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             row_sweeps<T>(c, l, u, uld(l), fptr(l), fld(l), width, false, c->opt.nu1, true);
         else
             for (int s = 0; s < c->opt.nu1; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, false, tl, s == 0);
-        T* r = LevelPtr<T>::r(lv);
-        if (tl.tx == 64)
-            hipLaunchKernelGGL((k_residual<T, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                               LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), r, width, lv.nx, width);
-        else
-            hipLaunchKernelGGL((k_residual<T, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                               LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), r, width, lv.nx, width);
         Level& lc = c->levels[l + 1];
-        hipLaunchKernelGGL(k_restrict<T>, grid2(lc.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                           (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width);
+        if (width >= 32) {
+            const int nseg = (lc.nx + kRrSeg - 1) / kRrSeg;
+            hipLaunchKernelGGL(k_resid_restrict<T>, dim3(lc.nx * nseg), dim3(64 * ((width + 63) / 64)), 0, c->stream,
+                               LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), LevelPtr<T>::f(lc), width,
+                               lc.nx, width, nseg);
+        } else {
+            T* r = LevelPtr<T>::r(lv);
+            if (tl.tx == 64)
+                hipLaunchKernelGGL((k_residual<T, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                                   LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), r, width, lv.nx, width);
+            else
+                hipLaunchKernelGGL((k_residual<T, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                                   LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), r, width, lv.nx, width);
+            hipLaunchKernelGGL(k_restrict<T>, grid2(lc.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                               (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width);
+        }
     }
     if (Lc >= 0) {
         FusedLevels<T> fl{};
@@ -948,7 +1158,11 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     for (int l = Ltop - 1; l >= 0; --l) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
-        if (tl.tx == 64)
+        if (width >= 32) {
+            const int nseg = (lv.nx + kPrSeg - 1) / kPrSeg;
+            hipLaunchKernelGGL(k_prolong_rows<T>, dim3(lv.nx * nseg), dim3(64 * ((width + 63) / 64)), 0, c->stream,
+                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width, nseg);
+        } else if (tl.tx == 64)
             hipLaunchKernelGGL((k_prolong_add<T, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
                                (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width);
         else
