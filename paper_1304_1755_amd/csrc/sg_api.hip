@@ -661,6 +661,7 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
             for (int k = 0; k < m; ++k) kl[e * m + k] = hs.klcell[(size_t)k * ncell + e];
         }
         if ((rc = upload(c, &c->cell64, cm))) return fail(rc);
+        if ((rc = upload(c, &c->zeros, std::vector<double>(256, 0.0)))) return fail(rc);
         if ((rc = upload(c, &c->klcell, kl))) return fail(rc);
     }
     if ((rc = upload(c, &c->kinv, hs.coarse_inv))) return fail(rc);

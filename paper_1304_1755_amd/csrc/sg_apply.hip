@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(NS * 64)
 k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int ldr,
            Tout* __restrict__ Y, int ldy, const double* __restrict__ cell,
            const uint32_t* __restrict__ toff, const double* __restrict__ tcoef, int n, int W_in,
-           int W_out, int self, int seg, int nseg) {
+           int W_out, int self, double rsign, int seg, int nseg) {
     constexpr int MM = M > 0 ? M : 1;
     constexpr int LANES = NS * 64;
     constexpr int BUF = MM * LANES + 2;
@@ -70,7 +70,7 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     const int x0 = (lb - y * nseg) * seg;
     const int x1 = min(x0 + seg, nx);
     const int t = s * 64 + lane;
-    const bool has_in = s * 64 < W_in, has_out = s * 64 < W_out;  // uniform
+    const bool has_out = s * 64 < W_out;  // uniform
     const bool vin = t < W_in, vout = t < W_out;
 
     // this lane's partners: position 2k = alpha + e_k, 2k+1 = alpha - e_k
@@ -87,49 +87,72 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
         S[1][MM * LANES] = 0.0;
     }
 
-    // 4-column window w[row][c]: rows y-1, y, y+1.  Step x uses the columns
-    // x-1, x, x+1 held at c = (x-x0) .. (x-x0)+2 (mod 4) and prefetches column
-    // x+2 into the fourth; the walk is unrolled by 4 so the column roles and
-    // the LDS buffer parity are compile-time constants.
-    double w[3][4];
-    const bool in_slot = has_in;
-    auto load_col = [&](int c, int xc) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const int yy = y + r - 1;
-            const bool okc = in_slot && (xc >= 0) && (xc < nx) && (yy >= 0) && (yy < nx);  // uniform
-            const Tin* rowp = U + ((size_t)yy * nx + xc) * ldu;                           // uniform
-            w[r][c] = (okc && vin) ? ld_as_double(rowp + t) : 0.0;
-        }
+    // Window w[row][c] of mode vectors: rows y-1, y, y+1, columns x-1, x, x+1
+    // at step x.  Step x takes column x+1 (and R at x) from ring slot
+    // (x - x0) mod 4, filled four steps earlier, so the loads of the walk are
+    // in flight while earlier steps compute.  Load addresses are clamped into
+    // the grid and the value replaced by zero outside it, so the loads need
+    // no branches; the walk is unrolled by 4, which makes the slot and the
+    // LDS buffer parity compile-time constants.
+    constexpr int D = 4;
+    const int tci = vin ? t : (W_in > 0 ? W_in - 1 : 0);
+    const int tco = vout ? t : W_out - 1;
+    const int ydn = y > 0 ? y - 1 : 0, yup = y + 1 < nx ? y + 1 : nx - 1;
+    const bool rdn = y > 0, rup = y + 1 < nx;
+    auto ldU = [&](int yy, int xc) -> Tin {
+        const int xcl = min(max(xc, 0), nx - 1);
+        return U[((size_t)yy * nx + xcl) * ldu + tci];
     };
-    load_col(0, x0 - 1);
-    load_col(1, x0);
-    load_col(2, x0 + 1);
+    auto zU = [&](Tin v, bool rowok, int xc) -> double {
+        return (rowok && vin && xc >= 0 && xc < nx) ? (double)v : 0.0;
+    };
+    // R is never null here (a zero vector with ldr = 0 stands in when no
+    // right-hand side is given) and the output is R + rsign * (A U)
+    Tin qd[D], qc[D], qu[D];
+    double qr[D];
+    auto issue = [&](int k, int x) {  // column x+1 and R at x, for step x
+        qd[k] = ldU(ydn, x + 1);
+        qc[k] = ldU(y, x + 1);
+        qu[k] = ldU(yup, x + 1);
+        qr[k] = R[((size_t)y * nx + min(x, nx - 1)) * ldr + tco];
+    };
+    double w[3][3];
+    w[0][0] = zU(ldU(ydn, x0 - 1), rdn, x0 - 1);
+    w[1][0] = zU(ldU(y, x0 - 1), true, x0 - 1);
+    w[2][0] = zU(ldU(yup, x0 - 1), rup, x0 - 1);
+    w[0][1] = zU(ldU(ydn, x0), rdn, x0);
+    w[1][1] = zU(ldU(y, x0), true, x0);
+    w[2][1] = zU(ldU(yup, x0), rup, x0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) issue(k, x0 + k);
 
-    auto step = [&](auto cstep, int x) {
-        constexpr int c0 = decltype(cstep)::value;  // window column of x-1
-        constexpr int cW = c0 & 3, cC = (c0 + 1) & 3, cE = (c0 + 2) & 3, cN = (c0 + 3) & 3;
-        double* B = S[c0 & 1];
-        load_col(cN, x + 2);  // prefetch for the next step
+    auto step = [&](auto kstep, int x) {
+        constexpr int k = decltype(kstep)::value;  // ring slot and LDS buffer parity
+        double* B = S[k & 1];
+        w[0][2] = zU(qd[k], rdn, x + 1);
+        w[1][2] = zU(qc[k], true, x + 1);
+        w[2][2] = zU(qu[k], rup, x + 1);
+        const double rv = qr[k];
+        issue(k, x + D);  // clamped: past the segment these loads are harmless
         double s0 = 0.0;
-        if (has_in) {
+        {
             // four cells around the node: SW (x, y), SE (x+1, y), NW (x, y+1), NE (x+1, y+1)
             const double* cSW = cell + ((size_t)y * n + x) * (M + 1);
             const double* cSE = cSW + (M + 1);
             const double* cNW = cell + ((size_t)(y + 1) * n + x) * (M + 1);
             const double* cNE = cNW + (M + 1);
-            const double uc4 = 4.0 * w[1][cC];
-            const double rSW = fma(-2.0, w[0][cW], uc4 - (w[0][cC] + w[1][cW]));
-            const double rSE = fma(-2.0, w[0][cE], uc4 - (w[0][cC] + w[1][cE]));
-            const double rNW = fma(-2.0, w[2][cW], uc4 - (w[2][cC] + w[1][cW]));
-            const double rNE = fma(-2.0, w[2][cE], uc4 - (w[2][cC] + w[1][cE]));
+            const double uc4 = 4.0 * w[1][1];
+            const double rSW = fma(-2.0, w[0][0], uc4 - (w[0][1] + w[1][0]));
+            const double rSE = fma(-2.0, w[0][2], uc4 - (w[0][1] + w[1][2]));
+            const double rNW = fma(-2.0, w[2][0], uc4 - (w[2][1] + w[1][0]));
+            const double rNE = fma(-2.0, w[2][2], uc4 - (w[2][1] + w[1][2]));
             s0 = fma(cSW[0], rSW, fma(cSE[0], rSE, fma(cNW[0], rNW, cNE[0] * rNE)));
 #pragma unroll
-            for (int k = 1; k <= M; ++k)
-                B[(k - 1) * LANES + t] = fma(cSW[k], rSW, fma(cSE[k], rSE, fma(cNW[k], rNW, cNE[k] * rNE)));
+            for (int kk = 1; kk <= M; ++kk)
+                B[(kk - 1) * LANES + t] = fma(cSW[kk], rSW, fma(cSE[kk], rSE, fma(cNW[kk], rNW, cNE[kk] * rNE)));
         }
         // LDS writes done, then the block barrier (no global-memory wait: the
-        // prefetched column stays in flight)
+        // ring loads stay in flight)
         __builtin_amdgcn_s_waitcnt(0xC07F);
         __asm__ __volatile__("" ::: "memory");
         __builtin_amdgcn_s_barrier();
@@ -145,9 +168,13 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
             }
             if (vout) {
                 const size_t node = (size_t)y * nx + x;
-                if (R) acc = R[node * ldr + t] - acc;
-                st_from_double(Y + node * ldy + t, acc);
+                st_from_double(Y + node * ldy + t, fma(rsign, acc, rv));
             }
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            w[r][0] = w[r][1];
+            w[r][1] = w[r][2];
         }
     };
     using I0 = std::integral_constant<int, 0>;
@@ -165,42 +192,42 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
 
 template <typename Tin, typename Tout, int M, int NS>
 hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
-                    int ldy, const double* cell, int n) {
+                    int ldy, const double* cell, int n, double rsign) {
     const int nx = n - 1;
     const int seg = 32;
     const int nseg = (nx + seg - 1) / seg;
     const int blocks = nx * nseg;
     hipLaunchKernelGGL((k_sg_apply<M, NS, Tin, Tout>), dim3(blocks), dim3(NS * 64), 0, st,
                        (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out, pl.self,
-                       seg, nseg);
+                       rsign, seg, nseg);
     return hipGetLastError();
 }
 
 template <typename Tin, typename Tout, int M>
 hipError_t launch_ns(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
-                     int ldy, const double* cell, int n) {
+                     int ldy, const double* cell, int n, double rsign) {
     switch (pl.nslot) {
-        case 1: return launch_t<Tin, Tout, M, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 2: return launch_t<Tin, Tout, M, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 3: return launch_t<Tin, Tout, M, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 4: return launch_t<Tin, Tout, M, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
+        case 1: return launch_t<Tin, Tout, M, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 2: return launch_t<Tin, Tout, M, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 3: return launch_t<Tin, Tout, M, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 4: return launch_t<Tin, Tout, M, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename Tin, typename Tout>
 hipError_t launch_m(hipStream_t st, int m, const Plan& pl, const void* U, int ldu, const double* R, int ldr,
-                    void* Y, int ldy, const double* cell, int n) {
+                    void* Y, int ldy, const double* cell, int n, double rsign) {
     switch (m) {
-        case 0: return launch_ns<Tin, Tout, 0>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 1: return launch_ns<Tin, Tout, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 2: return launch_ns<Tin, Tout, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 3: return launch_ns<Tin, Tout, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 4: return launch_ns<Tin, Tout, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 5: return launch_ns<Tin, Tout, 5>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 6: return launch_ns<Tin, Tout, 6>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 7: return launch_ns<Tin, Tout, 7>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
-        case 8: return launch_ns<Tin, Tout, 8>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n);
+        case 0: return launch_ns<Tin, Tout, 0>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 1: return launch_ns<Tin, Tout, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 2: return launch_ns<Tin, Tout, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 3: return launch_ns<Tin, Tout, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 4: return launch_ns<Tin, Tout, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 5: return launch_ns<Tin, Tout, 5>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 6: return launch_ns<Tin, Tout, 6>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 7: return launch_ns<Tin, Tout, 7>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 8: return launch_ns<Tin, Tout, 8>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
     }
     return hipErrorInvalidValue;
 }
@@ -211,12 +238,18 @@ int launch_apply(sg_ctx* c, const Plan& pl, const void* U, int in_float, const d
                  int ldu, int ldy, int ldr) {
     hipError_t e;
     const int m = c->hs.m, n = c->hs.n;
+    // Y = R - A U, or Y = A U with a zero right-hand side
+    const double rsign = R ? -1.0 : 1.0;
+    if (!R) {
+        R = c->zeros;
+        ldr = 0;
+    }
     if (!in_float && !out_float)
-        e = launch_m<double, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n);
+        e = launch_m<double, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, rsign);
     else if (in_float && !out_float)
-        e = launch_m<float, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n);
+        e = launch_m<float, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, rsign);
     else if (in_float && out_float)
-        e = launch_m<float, float>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n);
+        e = launch_m<float, float>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, rsign);
     else {
         set_error("apply: double input with float output is not provided");
         return SG_EINVAL;
