@@ -51,12 +51,12 @@ __device__ __forceinline__ int remap_block_xcd(int b, int nb) {
 // coupling partners from the whole buffer.  Splitting the modes over waves
 // keeps each wave's coupling tables and 3x3 window small, so several blocks
 // share a CU and hide memory latency.
-template <int M, int NS, typename Tin, typename Tout>
+template <int M, int NS, typename Tin, typename Tout, bool HAS_R>
 __global__ void __launch_bounds__(NS * 64)
 k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int ldr,
            Tout* __restrict__ Y, int ldy, const double* __restrict__ cell,
            const uint32_t* __restrict__ toff, const double* __restrict__ tcoef, int n, int W_in,
-           int W_out, int self, double rsign, int seg, int nseg) {
+           int W_out, int self, const Tin* __restrict__ zin, int seg, int nseg) {
     constexpr int MM = M > 0 ? M : 1;
     constexpr int LANES = NS * 64;
     constexpr int BUF = MM * LANES + 2;
@@ -87,72 +87,71 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
         S[1][MM * LANES] = 0.0;
     }
 
-    // Window w[row][c] of mode vectors: rows y-1, y, y+1, columns x-1, x, x+1
-    // at step x.  Step x takes column x+1 (and R at x) from ring slot
-    // (x - x0) mod 4, filled four steps earlier, so the loads of the walk are
-    // in flight while earlier steps compute.  Load addresses are clamped into
-    // the grid and the value replaced by zero outside it, so the loads need
-    // no branches; the walk is unrolled by 4, which makes the slot and the
-    // LDS buffer parity compile-time constants.
-    constexpr int D = 4;
-    const int tci = vin ? t : (W_in > 0 ? W_in - 1 : 0);
-    const int tco = vout ? t : W_out - 1;
-    const int ydn = y > 0 ? y - 1 : 0, yup = y + 1 < nx ? y + 1 : nx - 1;
-    const bool rdn = y > 0, rup = y + 1 < nx;
-    auto ldU = [&](int yy, int xc) -> Tin {
-        const int xcl = min(max(xc, 0), nx - 1);
-        return U[((size_t)yy * nx + xcl) * ldu + tci];
-    };
-    auto zU = [&](Tin v, bool rowok, int xc) -> double {
-        return (rowok && vin && xc >= 0 && xc < nx) ? (double)v : 0.0;
-    };
-    // R is never null here (a zero vector with ldr = 0 stands in when no
-    // right-hand side is given) and the output is R + rsign * (A U)
-    Tin qd[D], qc[D], qu[D];
-    double qr[D];
-    auto issue = [&](int k, int x) {  // column x+1 and R at x, for step x
-        qd[k] = ldU(ydn, x + 1);
-        qc[k] = ldU(y, x + 1);
-        qu[k] = ldU(yup, x + 1);
-        qr[k] = R[((size_t)y * nx + min(x, nx - 1)) * ldr + tco];
-    };
-    double w[3][3];
-    w[0][0] = zU(ldU(ydn, x0 - 1), rdn, x0 - 1);
-    w[1][0] = zU(ldU(y, x0 - 1), true, x0 - 1);
-    w[2][0] = zU(ldU(yup, x0 - 1), rup, x0 - 1);
-    w[0][1] = zU(ldU(ydn, x0), rdn, x0);
-    w[1][1] = zU(ldU(y, x0), true, x0);
-    w[2][1] = zU(ldU(yup, x0), rup, x0);
+    // Circular window wb[row][c] of mode vectors, rows y-1, y, y+1: column
+    // x of the grid lives in wb[.][(x - x0 + 1) mod 8].  Step x reads columns
+    // x-1, x, x+1 and issues the loads of column x+1+D, so D columns are in
+    // flight while earlier steps compute; the walk is unrolled by 8, which
+    // makes every column role, the R slot and the LDS buffer parity a
+    // compile-time constant and the window needs no register moves.  A
+    // neighbour outside the grid is read from the zero vector zin (a
+    // wave-uniform choice of base pointer, so no per-value select), and lanes
+    // past W_in read a valid column: their values feed no partner.
+    constexpr int D = 4;   // columns in flight; D + 3 <= 8 columns are live
+    constexpr int C = 8;
+    const uint32_t tci = vin ? t : W_in - 1;
+    const uint32_t tco = vout ? t : W_out - 1;
+    Tin wb[3][C];
+    double qr[D];  // R at x lives in qr[(x - x0) mod D]
+    auto load_col = [&](int c, int xc) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) issue(k, x0 + k);
+        for (int r = 0; r < 3; ++r) {
+            const int yy = y + r - 1;
+            const bool inside = yy >= 0 && yy < nx && xc >= 0 && xc < nx;  // uniform
+            const Tin* rowp = inside ? U + ((size_t)yy * nx + xc) * ldu : zin;
+            wb[r][c] = rowp[tci];
+        }
+    };
+    auto load_r = [&](int c, int x) {
+        if (HAS_R) qr[c % D] = R[((size_t)y * nx + min(x, nx - 1)) * ldr + tco];
+    };
+    // columns x0-1 .. x0+D and R at x0 .. x0+D-1
+    load_col(0, x0 - 1);
+    load_col(1, x0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        load_col(2 + i, x0 + 1 + i);
+        load_r(i, x0 + i);
+    }
 
     auto step = [&](auto kstep, int x) {
-        constexpr int k = decltype(kstep)::value;  // ring slot and LDS buffer parity
-        double* B = S[k & 1];
-        w[0][2] = zU(qd[k], rdn, x + 1);
-        w[1][2] = zU(qc[k], true, x + 1);
-        w[2][2] = zU(qu[k], rup, x + 1);
-        const double rv = qr[k];
-        issue(k, x + D);  // clamped: past the segment these loads are harmless
-        double s0 = 0.0;
+        constexpr int j = decltype(kstep)::value;  // x - x0 mod 8
+        constexpr int cW = j % C, cC = (j + 1) % C, cE = (j + 2) % C, cL = (j + 2 + D) % C;
+        double* B = S[j & 1];
+        const double rv = HAS_R ? qr[j % D] : 0.0;
+        load_col(cL, x + 1 + D);  // past the segment: zero-vector or in-grid loads, harmless
+        load_r(j, x + D);  // the slot just read
+        const double wSW = (double)wb[0][cW], wS = (double)wb[0][cC], wSE = (double)wb[0][cE];
+        const double wW = (double)wb[1][cW], wc = (double)wb[1][cC], wE = (double)wb[1][cE];
+        const double wNW = (double)wb[2][cW], wN = (double)wb[2][cC], wNE = (double)wb[2][cE];
+        double s0;
         {
             // four cells around the node: SW (x, y), SE (x+1, y), NW (x, y+1), NE (x+1, y+1)
             const double* cSW = cell + ((size_t)y * n + x) * (M + 1);
             const double* cSE = cSW + (M + 1);
             const double* cNW = cell + ((size_t)(y + 1) * n + x) * (M + 1);
             const double* cNE = cNW + (M + 1);
-            const double uc4 = 4.0 * w[1][1];
-            const double rSW = fma(-2.0, w[0][0], uc4 - (w[0][1] + w[1][0]));
-            const double rSE = fma(-2.0, w[0][2], uc4 - (w[0][1] + w[1][2]));
-            const double rNW = fma(-2.0, w[2][0], uc4 - (w[2][1] + w[1][0]));
-            const double rNE = fma(-2.0, w[2][2], uc4 - (w[2][1] + w[1][2]));
+            const double uc4 = 4.0 * wc;
+            const double rSW = fma(-2.0, wSW, uc4 - (wS + wW));
+            const double rSE = fma(-2.0, wSE, uc4 - (wS + wE));
+            const double rNW = fma(-2.0, wNW, uc4 - (wN + wW));
+            const double rNE = fma(-2.0, wNE, uc4 - (wN + wE));
             s0 = fma(cSW[0], rSW, fma(cSE[0], rSE, fma(cNW[0], rNW, cNE[0] * rNE)));
 #pragma unroll
             for (int kk = 1; kk <= M; ++kk)
                 B[(kk - 1) * LANES + t] = fma(cSW[kk], rSW, fma(cSE[kk], rSE, fma(cNW[kk], rNW, cNE[kk] * rNE)));
         }
         // LDS writes done, then the block barrier (no global-memory wait: the
-        // ring loads stay in flight)
+        // window loads stay in flight)
         __builtin_amdgcn_s_waitcnt(0xC07F);
         __asm__ __volatile__("" ::: "memory");
         __builtin_amdgcn_s_barrier();
@@ -160,74 +159,82 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
         if (has_out) {
             double acc = self ? s0 : 0.0;
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
+            for (int jj = 0; jj < M; ++jj) {
                 // absent partners read the shared zero entry: unconditional
                 // gathers schedule better than skipping positions per wave
-                acc = fma(ce[2 * j], B[off[j] & 0xFFFFu], acc);
-                acc = fma(ce[2 * j + 1], B[off[j] >> 16], acc);
+                acc = fma(ce[2 * jj], B[off[jj] & 0xFFFFu], acc);
+                acc = fma(ce[2 * jj + 1], B[off[jj] >> 16], acc);
             }
             if (vout) {
                 const size_t node = (size_t)y * nx + x;
-                st_from_double(Y + node * ldy + t, fma(rsign, acc, rv));
+                st_from_double(Y + node * ldy + t, HAS_R ? rv - acc : acc);
             }
-        }
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            w[r][0] = w[r][1];
-            w[r][1] = w[r][2];
         }
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
-    for (int x = x0; x < x1; x += 4) {
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    using I6 = std::integral_constant<int, 6>;
+    using I7 = std::integral_constant<int, 7>;
+    for (int x = x0; x < x1; x += C) {
         // x, x1 are uniform, so every wave of the block meets the same barriers
         step(I0{}, x);
         if (x + 1 < x1) step(I1{}, x + 1);
         if (x + 2 < x1) step(I2{}, x + 2);
         if (x + 3 < x1) step(I3{}, x + 3);
+        if (x + 4 < x1) step(I4{}, x + 4);
+        if (x + 5 < x1) step(I5{}, x + 5);
+        if (x + 6 < x1) step(I6{}, x + 6);
+        if (x + 7 < x1) step(I7{}, x + 7);
     }
 }
 
 template <typename Tin, typename Tout, int M, int NS>
 hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
-                    int ldy, const double* cell, int n, double rsign) {
+                    int ldy, const double* cell, int n, const void* zin) {
     const int nx = n - 1;
     const int seg = 32;
     const int nseg = (nx + seg - 1) / seg;
     const int blocks = nx * nseg;
-    hipLaunchKernelGGL((k_sg_apply<M, NS, Tin, Tout>), dim3(blocks), dim3(NS * 64), 0, st,
-                       (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out, pl.self,
-                       rsign, seg, nseg);
+    if (R)
+        hipLaunchKernelGGL((k_sg_apply<M, NS, Tin, Tout, true>), dim3(blocks), dim3(NS * 64), 0, st,
+                           (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out,
+                           pl.self, (const Tin*)zin, seg, nseg);
+    else
+        hipLaunchKernelGGL((k_sg_apply<M, NS, Tin, Tout, false>), dim3(blocks), dim3(NS * 64), 0, st,
+                           (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out,
+                           pl.self, (const Tin*)zin, seg, nseg);
     return hipGetLastError();
 }
 
 template <typename Tin, typename Tout, int M>
 hipError_t launch_ns(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
-                     int ldy, const double* cell, int n, double rsign) {
+                     int ldy, const double* cell, int n, const void* zin) {
     switch (pl.nslot) {
-        case 1: return launch_t<Tin, Tout, M, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 2: return launch_t<Tin, Tout, M, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 3: return launch_t<Tin, Tout, M, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 4: return launch_t<Tin, Tout, M, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 1: return launch_t<Tin, Tout, M, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 2: return launch_t<Tin, Tout, M, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 3: return launch_t<Tin, Tout, M, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 4: return launch_t<Tin, Tout, M, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename Tin, typename Tout>
 hipError_t launch_m(hipStream_t st, int m, const Plan& pl, const void* U, int ldu, const double* R, int ldr,
-                    void* Y, int ldy, const double* cell, int n, double rsign) {
+                    void* Y, int ldy, const double* cell, int n, const void* zin) {
     switch (m) {
-        case 0: return launch_ns<Tin, Tout, 0>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 1: return launch_ns<Tin, Tout, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 2: return launch_ns<Tin, Tout, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 3: return launch_ns<Tin, Tout, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 4: return launch_ns<Tin, Tout, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 5: return launch_ns<Tin, Tout, 5>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 6: return launch_ns<Tin, Tout, 6>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 7: return launch_ns<Tin, Tout, 7>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
-        case 8: return launch_ns<Tin, Tout, 8>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, rsign);
+        case 0: return launch_ns<Tin, Tout, 0>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 1: return launch_ns<Tin, Tout, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 2: return launch_ns<Tin, Tout, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 3: return launch_ns<Tin, Tout, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 4: return launch_ns<Tin, Tout, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 5: return launch_ns<Tin, Tout, 5>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 6: return launch_ns<Tin, Tout, 6>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 7: return launch_ns<Tin, Tout, 7>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 8: return launch_ns<Tin, Tout, 8>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
     }
     return hipErrorInvalidValue;
 }
@@ -238,18 +245,14 @@ int launch_apply(sg_ctx* c, const Plan& pl, const void* U, int in_float, const d
                  int ldu, int ldy, int ldr) {
     hipError_t e;
     const int m = c->hs.m, n = c->hs.n;
-    // Y = R - A U, or Y = A U with a zero right-hand side
-    const double rsign = R ? -1.0 : 1.0;
-    if (!R) {
-        R = c->zeros;
-        ldr = 0;
-    }
+    // Y = R - A U, or Y = A U when R is null; c->zeros serves as the zero neighbour
+    const void* zin = c->zeros;
     if (!in_float && !out_float)
-        e = launch_m<double, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, rsign);
+        e = launch_m<double, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, zin);
     else if (in_float && !out_float)
-        e = launch_m<float, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, rsign);
+        e = launch_m<float, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, zin);
     else if (in_float && out_float)
-        e = launch_m<float, float>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, rsign);
+        e = launch_m<float, float>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, zin);
     else {
         set_error("apply: double input with float output is not provided");
         return SG_EINVAL;

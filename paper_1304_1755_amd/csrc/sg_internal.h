@@ -110,7 +110,7 @@ struct sg_ctx {
     double* cell64 = nullptr;   // n*n x (m+1), cell-major, pre-scaled by 1/6
     double* klcell = nullptr;   // n*n x m  b_k at cell centres, cell-major
     double* kinv = nullptr;     // N_c x N_c
-    double* zeros = nullptr;    // 256 zeros: the right-hand side of an apply without one
+    double* zeros = nullptr;    // 256 zeros: the value of grid neighbours outside the domain in the apply
     std::vector<sg::Level> levels;
     sg::Plan plan_full{};
     std::vector<sg::Plan> plan_down;  // index d = 1..p: level d-1 -> level d
