@@ -38,12 +38,14 @@ def apply_bytes(N, P, n, m, in_bytes=8, out_bytes=8):
     return N * P * (in_bytes + out_bytes) + 8 * n * n * (m + 1)
 
 
-def traffic_from_profile(kernel_src):
+def traffic_from_profile(kernel_src, config):
     """HBM bytes per apply launch from committed rocprofv3 counter runs, if the kernel is unchanged."""
-    path = os.path.join(ROOT, "profiles", "apply_c3_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"apply_{config}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    if rec.get("config") != config:
+        return None
     digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
     if rec.get("kernel_sha256") != digest:
         return None
@@ -81,10 +83,10 @@ def cpu_baseline(seconds=10.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3")
-    ap.add_argument("--burst", type=int, default=10, help="double applies timed per step")
+    ap.add_argument("--burst", type=int, default=12, help="double applies timed per step")
     ap.add_argument("--mode", default="full", choices=["full", "apply"],
                     help="apply: only the double apply loop (for profiler counter runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -139,7 +141,8 @@ def main():
             s.record(stream)
             prob.apply(U, Y)
             e.record(stream)
-        _, info = prob.solve(F, X, precond="tri", prec=sgbt.SG_MIXED, restart=30, rtol=1e-8, max_it=300)
+        _, info = prob.solve(F, X, precond="tri", prec=sgbt.SG_MIXED, restart=c["restart"], rtol=1e-8,
+                             max_it=300)
         if timed:
             torch.cuda.synchronize()
             return [s.elapsed_time(e) for s, e in ev], info
@@ -168,16 +171,17 @@ def main():
     # all-double solve of the same problem, same algorithm (outside the timed steps)
     d_solves = []
     for _ in range(max(1, args.steps)):
-        _, info = prob.solve(F, X, precond="tri", prec=sgbt.SG_F64, restart=30, rtol=1e-8, max_it=300)
+        _, info = prob.solve(F, X, precond="tri", prec=sgbt.SG_F64, restart=c["restart"], rtol=1e-8, max_it=300)
         d_solves.append(info)
         progress(f"double solve: {info['iters']} it {info['t_total_ms']:.1f} ms")
     torch.cuda.synchronize()
 
     avg_apply_ms = float(np.mean(apply_ms))
+    med_apply_ms = float(np.median(apply_ms))
     achieved = nbytes / (avg_apply_ms * 1e-3) / 1e9
     t_mixed = float(np.median([s["t_total_ms"] for s in solves])) / 1e3
     t_f64 = float(np.median([s["t_total_ms"] for s in d_solves])) / 1e3
-    traffic = traffic_from_profile(os.path.join(ROOT, "paper_1304_1755_amd", "csrc", "sg_apply.hip"))
+    traffic = traffic_from_profile(os.path.join(ROOT, "paper_1304_1755_amd", "csrc", "sg_apply.hip"), args.config)
     out = {
         "metric": METRIC,
         "value": achieved,
@@ -193,7 +197,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: Q1 {n + 1}x{n + 1} grid (N={N}), m={m}, p={c['p']}, P={P} "
                                f"({N * P} unknowns), sigma={c['sigma']}, L={c['corr_len']}; step = {args.burst} "
-                               f"double SG applies + one mixed B_T-FGMRES(30) V(2,2) solve to 1e-8",
+                               f"double SG applies + one mixed B_T-FGMRES({c['restart']}) V(2,2) solve to 1e-8",
                    "N": N, "P": P, "unknowns": N * P},
         "time_to_1e-8_s": {"mixed": t_mixed, "fp64": t_f64, "speedup_mixed_vs_fp64": t_f64 / t_mixed,
                            "iters_mixed": solves[-1]["iters"], "iters_fp64": d_solves[-1]["iters"],
@@ -202,7 +206,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sg_apply (double in/out)", "algorithmic_bytes_per_launch": nbytes,
-                     "avg_launch_ms": avg_apply_ms},
+                     "avg_launch_ms": avg_apply_ms, "median_launch_ms": med_apply_ms,
+                     "launches_timed": len(apply_ms)},
     }
     prob.close()
     if not args.no_cpu:

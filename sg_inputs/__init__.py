@@ -9,15 +9,16 @@ Layout of block vectors drawn here: (N, P) -- one row per interior node
 
 import numpy as np
 
-# Workload presets: cells per side, KL terms m, degree p, sigma, correlation length.
+# Workload presets: cells per side, KL terms m, degree p, sigma, correlation length, and the
+# GMRES restart length each workload names.
 CONFIGS = {
-    "c1": dict(n=32, m=2, p=2, sigma=0.3, corr_len=0.5),
-    "c2": dict(n=128, m=4, p=3, sigma=0.3, corr_len=0.5),
-    "c3": dict(n=512, m=6, p=4, sigma=0.4, corr_len=0.5),
-    "c3_65": dict(n=64, m=6, p=4, sigma=0.4, corr_len=0.5),
-    "c4": dict(n=1024, m=8, p=3, sigma=0.5, corr_len=0.25),
-    "c4_129": dict(n=128, m=8, p=3, sigma=0.5, corr_len=0.25),
-    "c5": dict(n=256, m=5, p=3, sigma=0.3, corr_len=0.5),
+    "c1": dict(n=32, m=2, p=2, sigma=0.3, corr_len=0.5, restart=30),
+    "c2": dict(n=128, m=4, p=3, sigma=0.3, corr_len=0.5, restart=30),
+    "c3": dict(n=512, m=6, p=4, sigma=0.4, corr_len=0.5, restart=30),
+    "c3_65": dict(n=64, m=6, p=4, sigma=0.4, corr_len=0.5, restart=30),
+    "c4": dict(n=1024, m=8, p=3, sigma=0.5, corr_len=0.25, restart=20),
+    "c4_129": dict(n=128, m=8, p=3, sigma=0.5, corr_len=0.25, restart=20),
+    "c5": dict(n=256, m=5, p=3, sigma=0.3, corr_len=0.5, restart=30),
 }
 
 

@@ -23,3 +23,18 @@ def to_host(t):
 
 def rel_max(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+_PROBLEMS = {}
+
+
+def oracle_problem(cfg):
+    """The oracle's problem for a named workload, built once per test process (the 1025^2 build
+    takes ~20 s)."""
+    import sg_inputs
+    from oracle import system
+    if cfg not in _PROBLEMS:
+        c = sg_inputs.CONFIGS[cfg]
+        _PROBLEMS.clear()
+        _PROBLEMS[cfg] = system.build_problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"])
+    return _PROBLEMS[cfg]

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import sg_inputs
-from gpu_util import note, rel_max, to_dev, to_host
+from gpu_util import oracle_problem, note, rel_max, to_dev, to_host
 from oracle import system
 
 pytestmark = pytest.mark.gpu
@@ -72,13 +72,13 @@ def test_rhs_is_e0_times_load():
     g.close()
 
 
-@pytest.mark.parametrize("cfg", ["c3"])
+@pytest.mark.parametrize("cfg", ["c3", "c4"])
 def test_apply_full_size_separable(cfg):
     note(f"apply full size separable {cfg}")
     import paper_1304_1755_amd as sgbt
     c = sg_inputs.CONFIGS[cfg]
     g = sgbt.Problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"])
-    o = system.build_problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"])
+    o = oracle_problem(cfg)
     V, W = sg_inputs.separable_factors(g.N, g.P, rank=2)
     U = V.T @ W                                     # (N, P)
     Y = to_host(g.apply(to_dev(U)))
