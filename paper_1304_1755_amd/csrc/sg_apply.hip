@@ -23,6 +23,7 @@
 // mode vectors slides along the row, so each step loads one new column.
 
 #include <type_traits>
+#include <utility>
 
 #include "sg_internal.h"
 
@@ -44,14 +45,23 @@ __device__ __forceinline__ int remap_block_xcd(int b, int nb) {
     return x * q + (x < r ? x : r) + i;
 }
 
-// One block per row segment; wave s of the block owns modes [64 s, 64 s + 64)
-// of every node in the segment.  Per node, every wave writes its K_k u
-// (k >= 1) into a block-shared LDS exchange buffer (double-buffered by node
-// parity), the block meets at one barrier, and every wave then gathers its
-// coupling partners from the whole buffer.  Splitting the modes over waves
-// keeps each wave's coupling tables and 3x3 window small, so several blocks
-// share a CU and hide memory latency.
-template <int M, int NS, typename Tin, typename Tout, bool HAS_R>
+constexpr int kApplyRows = 2;  // grid rows per workgroup
+
+template <typename F, int... J>
+__device__ __forceinline__ void unroll_steps(F&& f, std::integer_sequence<int, J...>) {
+    (f(std::integral_constant<int, J>{}), ...);
+}
+
+// One workgroup per segment of RW grid rows (a row pair for RW = 2); wave s
+// of the workgroup owns modes [64 s, 64 s + 64) of every node in the
+// segment.  Per column, every wave writes the K_k u (k >= 1) of its RW nodes
+// into a block-shared LDS exchange buffer, the workgroup meets at a barrier,
+// and every wave then gathers its coupling partners from the whole buffer.
+// Splitting the modes over waves keeps each wave's coupling tables and
+// window small, so several workgroups share a CU and hide memory latency;
+// two rows per workgroup share the window's middle rows and the cell row
+// between them, and halve the synchronizations per node.
+template <int M, int NS, int RW, typename Tin, typename Tout, bool HAS_R>
 __global__ void __launch_bounds__(NS * 64)
 k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int ldr,
            Tout* __restrict__ Y, int ldy, const double* __restrict__ cell,
@@ -59,15 +69,18 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
            int W_out, int self, const Tin* __restrict__ zin, int seg, int nseg) {
     constexpr int MM = M > 0 ? M : 1;
     constexpr int LANES = NS * 64;
-    constexpr int BUF = MM * LANES + 2;
-    __shared__ double S[2][BUF];
+    constexpr int NODE = MM * LANES + 2;      // exchange entries of one node (+ its zero entry)
+    constexpr int NBUF = RW == 1 ? 2 : 1;      // one row: double-buffered by column parity
+    __shared__ double S[NBUF][RW * NODE];
     const int lane = threadIdx.x & 63;
     const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wave's slot (uniform)
     const int nx = n - 1;
     const int lb = remap_block_xcd(blockIdx.x, gridDim.x);
-    if (lb >= nx * nseg) return;  // whole block
-    const int y = lb / nseg;
-    const int x0 = (lb - y * nseg) * seg;
+    const int nrb = (nx + RW - 1) / RW;
+    if (lb >= nrb * nseg) return;  // whole block
+    const int yb = lb / nseg;
+    const int y0 = yb * RW;
+    const int x0 = (lb - yb * nseg) * seg;
     const int x1 = min(x0 + seg, nx);
     const int t = s * 64 + lane;
     const bool has_out = s * 64 < W_out;  // uniform
@@ -82,37 +95,41 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
         ce[2 * j] = M > 0 ? tcoef[t * 2 * MM + 2 * j] : 0.0;
         ce[2 * j + 1] = M > 0 ? tcoef[t * 2 * MM + 2 * j + 1] : 0.0;
     }
-    if (threadIdx.x == 0) {
-        S[0][MM * LANES] = 0.0;  // shared zero entry for absent partners
-        S[1][MM * LANES] = 0.0;
-    }
+    if (threadIdx.x < RW * NBUF) S[threadIdx.x / RW][(threadIdx.x % RW) * NODE + MM * LANES] = 0.0;  // zero entries
 
-    // Circular window wb[row][c] of mode vectors, rows y-1, y, y+1: column
-    // x of the grid lives in wb[.][(x - x0 + 1) mod 8].  Step x reads columns
+    // Circular window wb[row][c] of mode vectors, rows y0-1 .. y0+RW: column
+    // x of the grid lives in wb[.][(x - x0 + 1) mod C].  Step x reads columns
     // x-1, x, x+1 and issues the loads of column x+1+D, so D columns are in
-    // flight while earlier steps compute; the walk is unrolled by 8, which
+    // flight while earlier steps compute; the walk is unrolled by C, which
     // makes every column role, the R slot and the LDS buffer parity a
     // compile-time constant and the window needs no register moves.  A
     // neighbour outside the grid is read from the zero vector zin (a
     // wave-uniform choice of base pointer, so no per-value select), and lanes
     // past W_in read a valid column: their values feed no partner.
-    constexpr int D = 4;   // columns in flight; D + 3 <= 8 columns are live
-    constexpr int C = 8;
+    constexpr int C = RW == 1 ? 8 : 6;
+    constexpr int D = C - 3;  // columns in flight; D + 3 columns are live
+    constexpr int NR = RW + 2;
     const uint32_t tci = vin ? t : W_in - 1;
     const uint32_t tco = vout ? t : W_out - 1;
-    Tin wb[3][C];
-    double qr[D];  // R at x lives in qr[(x - x0) mod D]
+    Tin wb[NR][C];
+    double qr[RW][D];  // R at (x, y0 + q) lives in qr[q][(x - x0) mod D]
     auto load_col = [&](int c, int xc) {
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const int yy = y + r - 1;
+        for (int r = 0; r < NR; ++r) {
+            const int yy = y0 + r - 1;
             const bool inside = yy >= 0 && yy < nx && xc >= 0 && xc < nx;  // uniform
             const Tin* rowp = inside ? U + ((size_t)yy * nx + xc) * ldu : zin;
             wb[r][c] = rowp[tci];
         }
     };
     auto load_r = [&](int c, int x) {
-        if (HAS_R) qr[c % D] = R[((size_t)y * nx + min(x, nx - 1)) * ldr + tco];
+        if (HAS_R) {
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                const int yq = min(y0 + q, nx - 1);
+                qr[q][c % D] = R[((size_t)yq * nx + min(x, nx - 1)) * ldr + tco];
+            }
+        }
     };
     // columns x0-1 .. x0+D and R at x0 .. x0+D-1
     load_col(0, x0 - 1);
@@ -124,31 +141,37 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     }
 
     auto step = [&](auto kstep, int x) {
-        constexpr int j = decltype(kstep)::value;  // x - x0 mod 8
+        constexpr int j = decltype(kstep)::value;  // x - x0 mod C
         constexpr int cW = j % C, cC = (j + 1) % C, cE = (j + 2) % C, cL = (j + 2 + D) % C;
-        double* B = S[j & 1];
-        const double rv = HAS_R ? qr[j % D] : 0.0;
+        double* B = S[NBUF == 2 ? (j & 1) : 0];
+        double rv[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) rv[q] = HAS_R ? qr[q][j % D] : 0.0;
         load_col(cL, x + 1 + D);  // past the segment: zero-vector or in-grid loads, harmless
-        load_r(j, x + D);  // the slot just read
-        const double wSW = (double)wb[0][cW], wS = (double)wb[0][cC], wSE = (double)wb[0][cE];
-        const double wW = (double)wb[1][cW], wc = (double)wb[1][cC], wE = (double)wb[1][cE];
-        const double wNW = (double)wb[2][cW], wN = (double)wb[2][cC], wNE = (double)wb[2][cE];
-        double s0;
-        {
-            // four cells around the node: SW (x, y), SE (x+1, y), NW (x, y+1), NE (x+1, y+1)
-            const double* cSW = cell + ((size_t)y * n + x) * (M + 1);
+        load_r(j, x + D);         // the slot just read
+        double s0[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            s0[q] = 0.0;
+            if (RW > 1 && y0 + q >= nx) break;  // uniform: no such row (its cells would lie outside)
+            // node (x, y0 + q); cells SW (x, y0+q), SE (x+1, y0+q), NW (x, y0+q+1), NE (x+1, y0+q+1)
+            const double wSW = (double)wb[q][cW], wS = (double)wb[q][cC], wSE = (double)wb[q][cE];
+            const double wW = (double)wb[q + 1][cW], wc = (double)wb[q + 1][cC], wE = (double)wb[q + 1][cE];
+            const double wNW = (double)wb[q + 2][cW], wN = (double)wb[q + 2][cC], wNE = (double)wb[q + 2][cE];
+            const double* cSW = cell + ((size_t)(y0 + q) * n + x) * (M + 1);
             const double* cSE = cSW + (M + 1);
-            const double* cNW = cell + ((size_t)(y + 1) * n + x) * (M + 1);
+            const double* cNW = cell + ((size_t)(y0 + q + 1) * n + x) * (M + 1);
             const double* cNE = cNW + (M + 1);
             const double uc4 = 4.0 * wc;
             const double rSW = fma(-2.0, wSW, uc4 - (wS + wW));
             const double rSE = fma(-2.0, wSE, uc4 - (wS + wE));
             const double rNW = fma(-2.0, wNW, uc4 - (wN + wW));
             const double rNE = fma(-2.0, wNE, uc4 - (wN + wE));
-            s0 = fma(cSW[0], rSW, fma(cSE[0], rSE, fma(cNW[0], rNW, cNE[0] * rNE)));
+            s0[q] = fma(cSW[0], rSW, fma(cSE[0], rSE, fma(cNW[0], rNW, cNE[0] * rNE)));
 #pragma unroll
             for (int kk = 1; kk <= M; ++kk)
-                B[(kk - 1) * LANES + t] = fma(cSW[kk], rSW, fma(cSE[kk], rSE, fma(cNW[kk], rNW, cNE[kk] * rNE)));
+                B[q * NODE + (kk - 1) * LANES + t] =
+                    fma(cSW[kk], rSW, fma(cSE[kk], rSE, fma(cNW[kk], rNW, cNE[kk] * rNE)));
         }
         // LDS writes done, then the block barrier (no global-memory wait: the
         // window loads stay in flight)
@@ -157,54 +180,57 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
         __builtin_amdgcn_s_barrier();
         __asm__ __volatile__("" ::: "memory");
         if (has_out) {
-            double acc = self ? s0 : 0.0;
 #pragma unroll
-            for (int jj = 0; jj < M; ++jj) {
-                // absent partners read the shared zero entry: unconditional
-                // gathers schedule better than skipping positions per wave
-                acc = fma(ce[2 * jj], B[off[jj] & 0xFFFFu], acc);
-                acc = fma(ce[2 * jj + 1], B[off[jj] >> 16], acc);
-            }
-            if (vout) {
-                const size_t node = (size_t)y * nx + x;
-                st_from_double(Y + node * ldy + t, HAS_R ? rv - acc : acc);
+            for (int q = 0; q < RW; ++q) {
+                if (RW > 1 && y0 + q >= nx) break;  // uniform: the last row pair of an odd grid
+                const double* Bq = B + q * NODE;
+                double acc = self ? s0[q] : 0.0;
+#pragma unroll
+                for (int jj = 0; jj < M; ++jj) {
+                    // absent partners read the node's zero entry: unconditional
+                    // gathers schedule better than skipping positions per wave
+                    acc = fma(ce[2 * jj], Bq[off[jj] & 0xFFFFu], acc);
+                    acc = fma(ce[2 * jj + 1], Bq[off[jj] >> 16], acc);
+                }
+                if (vout) {
+                    const size_t node = (size_t)(y0 + q) * nx + x;
+                    st_from_double(Y + node * ldy + t, HAS_R ? rv[q] - acc : acc);
+                }
             }
         }
+        if (NBUF == 1) {
+            // single buffer: every wave has gathered before the next column is written
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            __asm__ __volatile__("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            __asm__ __volatile__("" ::: "memory");
+        }
     };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    using I3 = std::integral_constant<int, 3>;
-    using I4 = std::integral_constant<int, 4>;
-    using I5 = std::integral_constant<int, 5>;
-    using I6 = std::integral_constant<int, 6>;
-    using I7 = std::integral_constant<int, 7>;
     for (int x = x0; x < x1; x += C) {
         // x, x1 are uniform, so every wave of the block meets the same barriers
-        step(I0{}, x);
-        if (x + 1 < x1) step(I1{}, x + 1);
-        if (x + 2 < x1) step(I2{}, x + 2);
-        if (x + 3 < x1) step(I3{}, x + 3);
-        if (x + 4 < x1) step(I4{}, x + 4);
-        if (x + 5 < x1) step(I5{}, x + 5);
-        if (x + 6 < x1) step(I6{}, x + 6);
-        if (x + 7 < x1) step(I7{}, x + 7);
+        unroll_steps(
+            [&](auto kj) {
+                constexpr int j = decltype(kj)::value;
+                if (j == 0 || x + j < x1) step(kj, x + j);
+            },
+            std::make_integer_sequence<int, C>{});
     }
 }
 
 template <typename Tin, typename Tout, int M, int NS>
 hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
                     int ldy, const double* cell, int n, const void* zin) {
+    constexpr int RW = kApplyRows;
     const int nx = n - 1;
     const int seg = 32;
     const int nseg = (nx + seg - 1) / seg;
-    const int blocks = nx * nseg;
+    const int blocks = (nx + RW - 1) / RW * nseg;
     if (R)
-        hipLaunchKernelGGL((k_sg_apply<M, NS, Tin, Tout, true>), dim3(blocks), dim3(NS * 64), 0, st,
+        hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, true>), dim3(blocks), dim3(NS * 64), 0, st,
                            (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out,
                            pl.self, (const Tin*)zin, seg, nseg);
     else
-        hipLaunchKernelGGL((k_sg_apply<M, NS, Tin, Tout, false>), dim3(blocks), dim3(NS * 64), 0, st,
+        hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, false>), dim3(blocks), dim3(NS * 64), 0, st,
                            (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out,
                            pl.self, (const Tin*)zin, seg, nseg);
     return hipGetLastError();
