@@ -855,7 +855,30 @@ __device__ __forceinline__ void own_smooth(const OwnNodes<T>& on, T* u, const T*
         }
 }
 
-// NT threads: at least the largest colour class of the top fused grid
+// u = Kinv f on the coarsest grid (u, f = u + N in LDS), in double: output i
+// is summed by a group of G threads (the largest power of two with G N <=
+// blockDim, at most 64) over j = g, g + G, ..., then reduced across the group.
+template <typename T>
+__device__ __forceinline__ void coarsest_solve(const double* __restrict__ kinv, T* u, int N) {
+    const T* f = u + N;
+    int G = 1;
+    while (G < 64 && 2 * G * N <= (int)blockDim.x) G *= 2;
+    const int rows = (int)blockDim.x / G;  // outputs per pass
+    const int g = threadIdx.x % G;
+    for (int i0 = 0; i0 < N; i0 += rows) {  // uniform trip count
+        const int i = i0 + (int)threadIdx.x / G;
+        double acc = 0.0;
+        if (i < N) {
+            const double* row = kinv + (size_t)i * N;
+            for (int j = g; j < N; j += G) acc = fma(row[j], (double)f[j], acc);
+        }
+        for (int o = G / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);  // groups lie inside a wavefront
+        if (i < N && g == 0) u[i] = (T)acc;  // u and f are separate arrays
+    }
+    __syncthreads();
+}
+
+// NT threads: at least the largest colour class of the top fused grid// NT threads: at least the largest colour class of the top fused grid
 // (32 x 32 for 63 x 63 float grids, 16 x 16 for 31 x 31 double grids)
 template <typename T>
 constexpr int fused4_threads() { return sizeof(T) == 4 ? 1024 : 256; }
@@ -907,18 +930,7 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_fused4(FusedLeve
         }
         __syncthreads();
     }
-    {
-        const int nx = fl.nx[L], N = nx * nx;
-        T* u = lds + fl.off[L];
-        const T* f = u + N;
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            const double* row = kinv + (size_t)i * N;
-            double acc = 0.0;
-            for (int j = 0; j < N; ++j) acc = fma(row[j], (double)f[j], acc);
-            u[i] = (T)acc;
-        }
-        __syncthreads();
-    }
+    coarsest_solve<T>(kinv, lds + fl.off[L], fl.nx[L] * fl.nx[L]);
     for (int l = L - 1; l >= 0; --l) {
         const int nx = fl.nx[l], N = nx * nx, nxc = fl.nx[l + 1];
         T* u = lds + fl.off[l];
