@@ -78,9 +78,12 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     const int lb = remap_block_xcd(blockIdx.x, gridDim.x);
     const int nrb = (nx + RW - 1) / RW;
     if (lb >= nrb * nseg) return;  // whole block
-    const int yb = lb / nseg;
+    // segment-major: the row blocks of one column segment are consecutive, so
+    // the workgroups that share a halo row run at the same time on one XCD
+    const int sgi = lb / nrb;
+    const int yb = lb - sgi * nrb;
     const int y0 = yb * RW;
-    const int x0 = (lb - yb * nseg) * seg;
+    const int x0 = sgi * seg;
     const int x1 = min(x0 + seg, nx);
     const int t = s * 64 + lane;
     const bool has_out = s * 64 < W_out;  // uniform
