@@ -176,7 +176,7 @@ __global__ void k_restrict(const T* __restrict__ r, int ldr, T* __restrict__ fc,
     fc[(size_t)node * ldc + mode] = acc;
 }
 
-// Residual and restriction in one pass for wide blocks (W >= 32 modes):
+// Residual and restriction in one pass for wide blocks (W >= 16 modes):
 // fc = R (f - K u) without storing the fine residual.  A workgroup walks a
 // segment of kRrSeg nodes of one coarse row Y; lanes are modes.  Per coarse
 // column X it forms the row-weighted fine residual c(x) = r(x, fy-1)/2 +
@@ -185,6 +185,8 @@ __global__ void k_restrict(const T* __restrict__ r, int ldr, T* __restrict__ fc,
 // Loads are clamped into the grid (zero outside) and issued a ring of steps
 // ahead; the stencils of the three fine rows are staged in LDS.
 constexpr int kRrSeg = 16;
+// narrowest block the walking transfer kernels take (narrower: one node per thread)
+constexpr int kWalkMinWidth = 16;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ sten, const T* __restrict__ u, int ldu,
@@ -313,7 +315,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
     }
 }
 
-// Bilinear prolongation added to u for wide blocks (W >= 32 modes): a
+// Bilinear prolongation added to u for wide blocks (W >= 16 modes): a
 // workgroup walks kPrSeg nodes of one fine row; lanes are modes.  The fine
 // row takes the coarse row it lies on (odd y) or the mean of the two it lies
 // between (even y); along the row, odd x takes the coarse value it lies on
@@ -1120,7 +1122,7 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
         else
             for (int s = 0; s < c->opt.nu1; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, false, tl, s == 0);
         Level& lc = c->levels[l + 1];
-        if (width >= 32) {
+        if (width >= kWalkMinWidth) {
             const int nseg = (lc.nx + kRrSeg - 1) / kRrSeg;
             hipLaunchKernelGGL(k_resid_restrict<T>, dim3(lc.nx * nseg), dim3(64 * ((width + 63) / 64)), 0, c->stream,
                                LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), LevelPtr<T>::f(lc), width,
@@ -1170,7 +1172,7 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     for (int l = Ltop - 1; l >= 0; --l) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
-        if (width >= 32) {
+        if (width >= kWalkMinWidth) {
             const int nseg = (lv.nx + kPrSeg - 1) / kPrSeg;
             hipLaunchKernelGGL(k_prolong_rows<T>, dim3(lv.nx * nseg), dim3(64 * ((width + 63) / 64)), 0, c->stream,
                                (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width, nseg);

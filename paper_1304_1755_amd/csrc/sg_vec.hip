@@ -149,16 +149,17 @@ __global__ void __launch_bounds__(256) k_update2(const double* __restrict__ Q, s
     }
 }
 
-// out[i] = sum_b partial[b][i], fixed order
+// out[i] = sum_b partial[b][i] in a fixed order; workgroup i sums column i
+// (launched with one workgroup per column)
 __global__ void k_reduce_partials(const double* __restrict__ partial, int nblocks, int width, int ldp,
                                   double* __restrict__ out) {
     __shared__ double sh[4];
-    for (int i = 0; i < width; ++i) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[(size_t)b * ldp + i];
-        const double t = block_sum(v, sh);
-        if (threadIdx.x == 0) out[i] = t;
-    }
+    const int i = blockIdx.x;
+    if (i >= width) return;  // uniform over the workgroup
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[(size_t)b * ldp + i];
+    const double t = block_sum(v, sh);
+    if (threadIdx.x == 0) out[i] = t;
 }
 
 __global__ void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b, size_t len,
@@ -386,7 +387,7 @@ hipError_t vec_dots2(hipStream_t s, const double* Q, size_t stride, int nv, cons
             hipLaunchKernelGGL(k_dots2<8>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, u, w, len, partial);
         else
             hipLaunchKernelGGL(k_dots2<kDc>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, u, w, len, partial);
-        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, kDcLd, kDcLd,
+        hipLaunchKernelGGL(k_reduce_partials, dim3(kDcLd), dim3(256), 0, s, partial, kRedBlocks, kDcLd, kDcLd,
                            out + (size_t)ch * kDcLd);
     }
     return hipGetLastError();
@@ -466,7 +467,7 @@ hipError_t vec_rhs(hipStream_t s, double* F, int N, int P, double h2) {
 hipError_t vec_qoi(hipStream_t s, const double* U, const double* wS, int N, int P, double* partial, double* q,
                    double* J, double* coef) {
     hipLaunchKernelGGL(k_qoi_partial, dim3(kRedBlocks), dim3(256), 0, s, U, wS, N, P, partial, P);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, P, P, q);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(P), dim3(256), 0, s, partial, kRedBlocks, P, P, q);
     hipLaunchKernelGGL(k_qoi_finish, dim3(1), dim3(256), 0, s, q, P, J, coef);
     return hipGetLastError();
 }
@@ -494,7 +495,7 @@ hipError_t vec_grad_params(hipStream_t s, const double* dc, const double* kl, co
                            int m, double* partial, double* Tk, double* out_params, double* out_a0) {
     if (m > 0) {
         hipLaunchKernelGGL(k_grad_kl_partial, dim3(kRedBlocks), dim3(256), 0, s, dc, kl, n * n, m, partial);
-        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, kRedBlocks, m, 16, Tk);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(m), dim3(256), 0, s, partial, kRedBlocks, m, 16, Tk);
     }
     hipLaunchKernelGGL(k_grad_kl_finish, dim3(1), dim3(64), 0, s, Tk, amps, sigma, m, out_params);
     const int nn = (n - 1) * (n - 1);
