@@ -184,16 +184,17 @@ __global__ void k_restrict(const T* __restrict__ r, int ldr, T* __restrict__ fc,
 // of five fine rows of u, and then fc(X) = c(2X)/2 + c(2X+1) + c(2X+2)/2.
 // Loads are clamped into the grid (zero outside) and issued a ring of steps
 // ahead; the stencils of the three fine rows are staged in LDS.
-constexpr int kRrSeg = 16;
+constexpr int kRrSeg = 16;       // coarse nodes per segment on the fine levels
+constexpr int kRrSegShort = 4;   // on coarse levels, where long walks leave too few workgroups
 // narrowest block the walking transfer kernels take (narrower: one node per thread)
 constexpr int kWalkMinWidth = 16;
 
-template <typename T>
+template <typename T, int SEG>
 __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ sten, const T* __restrict__ u, int ldu,
                                                         const T* __restrict__ f, int ldf, T* __restrict__ fc,
                                                         int ldc, int nxc, int width, int nseg) {
     constexpr int D = 2;
-    constexpr int NC = 2 * kRrSeg + 1;                 // staged fine columns 2 X0 .. 2 X0 + 2 kRrSeg
+    constexpr int NC = 2 * SEG + 1;                 // staged fine columns 2 X0 .. 2 X0 + 2 SEG
     constexpr int SP = sizeof(T) == 4 ? 12 : 10;
     __shared__ T stl[3 * NC * SP];
     const int lane = threadIdx.x & 63;
@@ -204,8 +205,8 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb >= nxc * nseg) return;  // uniform over the workgroup
     const int Y = lb / nseg;
-    const int X0 = (lb - Y * nseg) * kRrSeg;
-    const int X1 = min(X0 + kRrSeg, nxc);
+    const int X0 = (lb - Y * nseg) * SEG;
+    const int X1 = min(X0 + SEG, nxc);
     const int nxf = 2 * nxc + 1;
     const int fy = 2 * Y + 1;
     const int xb = 2 * X0;  // first fine column of the walk
@@ -279,7 +280,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
     }
     T cprev = colres(xb, W, f0);
 #pragma unroll
-    for (int i = 0; i < kRrSeg; ++i) {
+    for (int i = 0; i < SEG; ++i) {
         const int s = i % D;
         const int X = X0 + i;
         const int x = 2 * X;
@@ -300,7 +301,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
             fa[k] = qf1[s][k];
             fb[k] = qf2[s][k];
         }
-        if (i + D < kRrSeg) issue(i + D, s);
+        if (i + D < SEG) issue(i + D, s);
         if (X < X1) {
             const T c1 = colres(x + 1, A, fa);
             const T c2 = colres(x + 2, Bw, fb);
@@ -321,13 +322,14 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
 // between (even y); along the row, odd x takes the coarse value it lies on
 // and even x the mean of its two neighbours.  Loads are clamped (zero
 // outside the coarse grid) and issued a ring of steps ahead.
-constexpr int kPrSeg = 32;
+constexpr int kPrSeg = 32;       // fine nodes per segment on the fine levels
+constexpr int kPrSegShort = 8;   // on coarse levels
 
-template <typename T>
+template <typename T, int SEG>
 __global__ void __launch_bounds__(256) k_prolong_rows(const T* __restrict__ ec, int ldc, T* __restrict__ u, int ldu,
                                                       int nxf, int width, int nseg) {
     constexpr int D = 4;
-    constexpr int NIT = kPrSeg / 2;
+    constexpr int NIT = SEG / 2;
     const int lane = threadIdx.x & 63;
     const int s_w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = s_w * 64 + lane;
@@ -336,8 +338,8 @@ __global__ void __launch_bounds__(256) k_prolong_rows(const T* __restrict__ ec, 
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb >= nxf * nseg) return;
     const int y = lb / nseg;
-    const int x0 = (lb - y * nseg) * kPrSeg;  // even
-    const int x1 = min(x0 + kPrSeg, nxf);
+    const int x0 = (lb - y * nseg) * SEG;  // even
+    const int x1 = min(x0 + SEG, nxf);
     const int nxc = (nxf - 1) / 2;
     int ya, yb;
     T wy;
@@ -443,20 +445,21 @@ __global__ void k_coarse(const double* __restrict__ kinv, const T* __restrict__ 
 // the node lies outside, so the loads carry no branches and stay in flight
 // while earlier steps compute.  The segment's stencils are staged in LDS
 // once per workgroup.
-constexpr int kRowSeg = 32;
+constexpr int kRowSeg = 32;       // nodes per segment on the fine levels
+constexpr int kRowSegShort = 8;   // on coarse levels, where long walks leave too few workgroups
 
 template <typename T>
 constexpr int gs_ring() { return sizeof(T) == 4 ? 4 : 3; }
 
-template <typename T, bool OWNZ>
+template <typename T, bool OWNZ, int SEG>
 __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, const T* __restrict__ A, int lda,
                                                  const T* __restrict__ V, int ldv, const T* __restrict__ f, int ldf,
                                                  T* __restrict__ B, int ldb, int nx, int width, int py, int fx,
                                                  int vert_zero, int nseg, int nrows) {
-    constexpr int NIT = kRowSeg / 2;          // S nodes per segment
+    constexpr int NIT = SEG / 2;          // S nodes per segment
     constexpr int D = gs_ring<T>();
     constexpr int SP = sizeof(T) == 4 ? 12 : 10;  // LDS pitch of a staged stencil
-    __shared__ T stl[(kRowSeg + 2) * SP];
+    __shared__ T stl[(SEG + 2) * SP];
     const int lane = threadIdx.x & 63;
     const int s_w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = s_w * 64 + lane;
@@ -466,12 +469,12 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     if (lb >= nrows * nseg) return;     // uniform over the workgroup
     const int r = lb / nseg;
     const int y = py + 2 * r;
-    const int x0 = (lb - r * nseg) * kRowSeg;  // even
-    const int x1 = min(x0 + kRowSeg, nx);
+    const int x0 = (lb - r * nseg) * SEG;  // even
+    const int x1 = min(x0 + SEG, nx);
     const bool has_dn = y > 0 && !vert_zero, has_up = y + 1 < nx && !vert_zero;
     const int ydn = y > 0 ? y - 1 : y, yup = y + 1 < nx ? y + 1 : y;
-    // stencils of columns x0-1 .. x0+kRowSeg (clamped), column c at stl[c * SP]
-    for (int i = threadIdx.x; i < (kRowSeg + 2) * 9; i += blockDim.x) {
+    // stencils of columns x0-1 .. x0+SEG (clamped), column c at stl[c * SP]
+    for (int i = threadIdx.x; i < (SEG + 2) * 9; i += blockDim.x) {
         const int c = i / 9, e = i - c * 9;
         const int x = min(max(x0 - 1 + c, 0), nx - 1);
         stl[c * SP + e] = sten[((size_t)y * nx + x) * 9 + e];
@@ -1029,6 +1032,11 @@ void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, boo
     }
 }
 
+// A walk of a long segment per workgroup keeps the data of a segment in
+// flight, but on a coarse grid it leaves too few wavefronts to fill the chip:
+// below this many wavefronts the short-segment form of a walking kernel runs.
+constexpr int kMinWalkWaves = 2048;
+
 // nu four-colour sweeps by row phases with ping-pong between u and the
 // level's second buffer; returns with the result in u.  zero_start: u holds
 // the zero initial guess (not read).
@@ -1039,8 +1047,10 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
     const int nx = lv.nx;
     T* alt = LevelPtr<T>::u2(lv);
     const int lda_alt = width;
-    const int nseg = (nx + kRowSeg - 1) / kRowSeg;
     const int nws = (width + 63) / 64;
+    const bool shortw = (long)((nx + 1) / 2) * ((nx + kRowSeg - 1) / kRowSeg) * nws < kMinWalkWaves;
+    const int seg = shortw ? kRowSegShort : kRowSeg;
+    const int nseg = (nx + seg - 1) / seg;
     T* src = u;
     int lds = ldu;
     T* dst = alt;
@@ -1056,14 +1066,15 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
             const int ldv = ph == 0 ? lds : ldd;
             const int vzero = (ph == 0 && own_zero) ? 1 : 0;
             if (width >= 32) {
+                auto go = [&](auto kern) {
+                    hipLaunchKernelGGL(kern, dim3(nrows * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv),
+                                       (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py, fx, vzero, nseg,
+                                       nrows);
+                };
                 if (own_zero)
-                    hipLaunchKernelGGL((k_gs_rows<T, true>), dim3(nrows * nseg), dim3(64 * nws), 0, c->stream,
-                                       LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width,
-                                       py, fx, vzero, nseg, nrows);
+                    shortw ? go(k_gs_rows<T, true, kRowSegShort>) : go(k_gs_rows<T, true, kRowSeg>);
                 else
-                    hipLaunchKernelGGL((k_gs_rows<T, false>), dim3(nrows * nseg), dim3(64 * nws), 0, c->stream,
-                                       LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width,
-                                       py, fx, vzero, nseg, nrows);
+                    shortw ? go(k_gs_rows<T, false, kRowSegShort>) : go(k_gs_rows<T, false, kRowSeg>);
             } else {
                 int wl = 0;
                 while ((1 << wl) < width) ++wl;
@@ -1123,10 +1134,13 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             for (int s = 0; s < c->opt.nu1; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, false, tl, s == 0);
         Level& lc = c->levels[l + 1];
         if (width >= kWalkMinWidth) {
-            const int nseg = (lc.nx + kRrSeg - 1) / kRrSeg;
-            hipLaunchKernelGGL(k_resid_restrict<T>, dim3(lc.nx * nseg), dim3(64 * ((width + 63) / 64)), 0, c->stream,
-                               LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), LevelPtr<T>::f(lc), width,
-                               lc.nx, width, nseg);
+            const int nws = (width + 63) / 64;
+            const bool shortw = (long)lc.nx * ((lc.nx + kRrSeg - 1) / kRrSeg) * nws < kMinWalkWaves;
+            const int seg = shortw ? kRrSegShort : kRrSeg;
+            const int nseg = (lc.nx + seg - 1) / seg;
+            hipLaunchKernelGGL((shortw ? k_resid_restrict<T, kRrSegShort> : k_resid_restrict<T, kRrSeg>),
+                               dim3(lc.nx * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv), (const T*)u,
+                               uld(l), fptr(l), fld(l), LevelPtr<T>::f(lc), width, lc.nx, width, nseg);
         } else {
             T* r = LevelPtr<T>::r(lv);
             if (tl.tx == 64)
@@ -1173,9 +1187,13 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
         if (width >= kWalkMinWidth) {
-            const int nseg = (lv.nx + kPrSeg - 1) / kPrSeg;
-            hipLaunchKernelGGL(k_prolong_rows<T>, dim3(lv.nx * nseg), dim3(64 * ((width + 63) / 64)), 0, c->stream,
-                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width, nseg);
+            const int nws = (width + 63) / 64;
+            const bool shortw = (long)lv.nx * ((lv.nx + kPrSeg - 1) / kPrSeg) * nws < kMinWalkWaves;
+            const int seg = shortw ? kPrSegShort : kPrSeg;
+            const int nseg = (lv.nx + seg - 1) / seg;
+            hipLaunchKernelGGL((shortw ? k_prolong_rows<T, kPrSegShort> : k_prolong_rows<T, kPrSeg>), dim3(lv.nx * nseg),
+                               dim3(64 * nws), 0, c->stream, (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u,
+                               uld(l), lv.nx, width, nseg);
         } else if (tl.tx == 64)
             hipLaunchKernelGGL((k_prolong_add<T, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
                                (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width);
