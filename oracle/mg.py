@@ -6,8 +6,9 @@ V-cycle"; Sec. 6: one V(2,2) cycle with point Gauss-Seidel smoothing).  It
 names no other component, so the readings used here are:
 
 * grids n, n/2, ..., n_c cells per side; bilinear prolongation P (exact
-  interpolation of the coarse Q1 space), restriction R = P^T, Galerkin coarse
-  operators K_{l-1} = P^T K_l P;
+  interpolation of the coarse Q1 space; for the P1 triangulation of Sec. 6,
+  transfer="p1" gives linear interpolation on the triangles), restriction
+  R = P^T, Galerkin coarse operators K_{l-1} = P^T K_l P;
 * Gauss-Seidel by colours of the interior grid indices (I, J):
   'four'  : colour (I mod 2) + 2 (J mod 2), a true Gauss-Seidel sweep for the
             9-point stencil because equal colours never touch;
@@ -44,6 +45,36 @@ def prolongation(nc):
     return sp.kron(p1, p1, format="csr")
 
 
+def prolongation_p1(nc):
+    """Linear interpolation on the triangulation whose squares are split south-west to
+    north-east (the natural P1 transfer): a fine node on a coarse node copies it, one on a
+    horizontal, vertical or diagonal coarse edge takes the mean of that edge's two ends.
+    Interior x-fastest numbering on both grids; Dirichlet coarse nodes drop out."""
+    nf = 2 * nc
+    rows, cols, vals = [], [], []
+
+    def coarse(i, j):
+        return (j - 1) * (nc - 1) + (i - 1) if 1 <= i <= nc - 1 and 1 <= j <= nc - 1 else None
+
+    for J in range(1, nf):
+        for I in range(1, nf):
+            if I % 2 == 0 and J % 2 == 0:
+                ends = [(I // 2, J // 2, 1.0)]
+            elif J % 2 == 0:                      # horizontal coarse edge
+                ends = [((I - 1) // 2, J // 2, 0.5), ((I + 1) // 2, J // 2, 0.5)]
+            elif I % 2 == 0:                      # vertical coarse edge
+                ends = [(I // 2, (J - 1) // 2, 0.5), (I // 2, (J + 1) // 2, 0.5)]
+            else:                                 # diagonal: south-west and north-east corners
+                ends = [((I - 1) // 2, (J - 1) // 2, 0.5), ((I + 1) // 2, (J + 1) // 2, 0.5)]
+            for i, j, w in ends:
+                c = coarse(i, j)
+                if c is not None:
+                    rows.append((J - 1) * (nf - 1) + (I - 1))
+                    cols.append(c)
+                    vals.append(w)
+    return sp.csr_matrix((vals, (rows, cols)), shape=((nf - 1) ** 2, (nc - 1) ** 2))
+
+
 def colours(n, mode):
     """List of index arrays, one per colour, in pre-smoothing order."""
     I, J = np.meshgrid(np.arange(1, n), np.arange(1, n), indexing="xy")
@@ -59,16 +90,17 @@ def colours(n, mode):
 
 
 class Hierarchy:
-    def __init__(self, K0, n, coarsest=8, colour_mode="four", nu1=2, nu2=2):
+    def __init__(self, K0, n, coarsest=8, colour_mode="four", nu1=2, nu2=2, transfer="bilinear"):
         assert n % coarsest == 0 and ((n // coarsest) & (n // coarsest - 1)) == 0
         self.colour_mode = colour_mode
         self.nu1, self.nu2 = nu1, nu2
         self.ns = [n]
         self.K = [K0.tocsr()]
         self.P = []
+        make_p = {"bilinear": prolongation, "p1": prolongation_p1}[transfer]
         while self.ns[-1] > coarsest:
             nc = self.ns[-1] // 2
-            P = prolongation(nc)
+            P = make_p(nc)
             self.P.append(P)
             Kc = (P.T @ self.K[-1] @ P).tocsr()
             Kc.sum_duplicates()
