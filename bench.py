@@ -181,7 +181,7 @@ def main():
     achieved = nbytes / (avg_apply_ms * 1e-3) / 1e9
     t_mixed = float(np.median([s["t_total_ms"] for s in solves])) / 1e3
     t_f64 = float(np.median([s["t_total_ms"] for s in d_solves])) / 1e3
-    traffic = traffic_from_profile(os.path.join(ROOT, "paper_1304_1755_amd", "csrc", "sg_apply.hip"), args.config)
+    traffic = traffic_from_profile(os.path.join(ROOT, "paper_1304_1755_amd", "csrc", "sg_apply_kernel.h"), args.config)
     out = {
         "metric": METRIC,
         "value": achieved,

@@ -7,10 +7,19 @@
  *
  *     A U = F,   A = G_0 (x) K_0 + sum_{k=1..m} G_k (x) K_k          (Sec. 3.1, eq. (tensor-product))
  *
- * for -div(a grad u) = 1 on the unit square with zero Dirichlet data, Q1
- * elements on a uniform n x n grid, a truncated Karhunen-Loeve coefficient
- * a = a0 + sigma sum_k s_k b_k(x) xi_k with xi_k ~ U[-1, 1] (Sec. 2.1, eq.
- * (truncated-KLE)) and orthonormal Legendre chaos of total degree p (Sec. 2.2).
+ * for -div(a grad u) = f with zero Dirichlet data on a uniform n x n grid, a
+ * truncated Karhunen-Loeve coefficient a = a0 + sigma sum_k s_k b_k(x) xi_k
+ * (Sec. 2.1, eq. (truncated-KLE)) and orthonormal Legendre chaos of total
+ * degree p (Sec. 2.2).  Two discretisations (sg_options.discretization):
+ *   SG_DISC_Q1: bilinear elements on the unit square, f = 1, xi_k ~ U[-1, 1],
+ *     cell-centre coefficients, bilinear multigrid transfer;
+ *   SG_DISC_P1: the setting of Sec. 6: linear elements on the triangulation
+ *     that splits every square along its south-west to north-east diagonal,
+ *     D = (-1/2, 1/2)^2, f = 2 (1/2 - x^2 - y^2), xi_k uniform with variance
+ *     one (so the coupling entries of G_k, k >= 1, carry a factor sqrt 3),
+ *     one coefficient value per triangle (at its centroid), and the linear
+ *     interpolation of the triangulation as multigrid transfer.  Every K_k is
+ *     then a 5-point operator.
  *
  * Data layout of every block vector ("N x P, node-major"): N = (n-1)^2
  * interior nodes numbered x-fastest, P = (m+p)!/(m!p!) chaos modes in graded
@@ -38,7 +47,8 @@ extern "C" {
 #endif
 
 #define SG_OK 0
-#define SG_WNOTCOERCIVE 1 /* setup: min over cells of c_0 - sum_k |c_k| is <= 0 (A may be indefinite) */
+#define SG_WNOTCOERCIVE 1 /* setup: min over elements of c_0 - xi_max sum_k |c_k| is <= 0, with xi_max = 1
+                             (SG_DISC_Q1) or sqrt 3 (SG_DISC_P1): A may be indefinite */
 #define SG_EINVAL (-1)    /* invalid argument (sizes, null pointers, unsupported combination) */
 #define SG_ENOMEM (-2)    /* device or host allocation failed */
 #define SG_EHIP (-3)      /* a HIP runtime call failed; see sg_last_error() */
@@ -54,6 +64,10 @@ extern "C" {
 #define SG_COLOUR_FOUR 0 /* colour (I mod 2) + 2 (J mod 2): exact Gauss-Seidel for the 9-point stencil */
 #define SG_COLOUR_RB 1   /* colour (I + J) mod 2, each colour updated from its start-of-colour values */
 
+/* discretisations (see above) */
+#define SG_DISC_Q1 0
+#define SG_DISC_P1 1
+
 typedef struct sg_ctx sg_ctx;
 
 typedef struct {
@@ -65,6 +79,8 @@ typedef struct {
     int colour_mode;    /* SG_COLOUR_FOUR or SG_COLOUR_RB */
     int nu1, nu2;       /* pre- and post-smoothing sweeps of the V-cycle, 0..8 */
     int coarsest_cells; /* cells per side of the coarsest grid (>= 2); equal to n_cells gives exact K_0 solves */
+    int discretization; /* SG_DISC_Q1 (0) or SG_DISC_P1 (1); SG_DISC_P1 takes a0 = 1 (a0_nodal NULL),
+                           SG_COLOUR_FOUR, and has no sg_qoi / sg_qoi_grad */
 } sg_options;
 
 typedef struct {
@@ -113,12 +129,17 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
 int sg_query(const sg_ctx* ctx, int* N, int* P, int* level_offsets, int* multi_index,
              double* kl_lambda, double* a_min_h);
 
-/* Host copy of the cell coefficients c_{k,e} (Sec. 3.1, eq. (def-stiffness)
- * with cell-constant coefficients): (m+1) rows of n*n cells, cell (cx, cy) at
- * cy*n + cx.  out: host, (m+1)*n*n doubles. */
+/* Host copy of the element coefficients c_{k,e} (Sec. 3.1, eq. (def-stiffness)
+ * with element-constant coefficients).  SG_DISC_Q1: (m+1) rows of n*n cells,
+ * cell (cx, cy) at cy*n + cx; out: host, (m+1)*n*n doubles.  SG_DISC_P1:
+ * (m+1) rows of 2*n*n triangles, the lower triangle (SW, SE, NE corners) of
+ * cell (cx, cy) at cy*n + cx and its upper triangle (SW, NE, NW) at
+ * n*n + cy*n + cx; out: host, (m+1)*2*n*n doubles. */
 int sg_get_cell_coeffs(const sg_ctx* ctx, double* out);
 
-/* F = e_0 (x) f_h for f = 1 (Sec. 2.2 Galerkin right-hand side). F: device, N*P doubles. */
+/* F = e_0 (x) f_h (Sec. 2.2 Galerkin right-hand side): f = 1 for SG_DISC_Q1,
+ * f = 2 (1/2 - x^2 - y^2) integrated exactly for SG_DISC_P1 (Sec. 6).
+ * F: device, N*P doubles. */
 int sg_rhs(sg_ctx* ctx, double* F);
 
 /* Y = A U, matrix-free (Sec. 3.1, eq. (tensor-product)).
@@ -155,13 +176,15 @@ int sg_precond_sym(sg_ctx* ctx, const void* R, void* Z, int prec);
  * SG_ENOTCONV or SG_ENAN (U holds the last iterate) or an error. */
 int sg_solve(sg_ctx* ctx, const double* F, double* U, const sg_solve_opts* opts, sg_solve_info* info);
 
-/* QoI of eq. (PCE_u) statistics: q_a = w_S . U_a with w_S the exact
+/* SG_DISC_Q1 only (SG_EINVAL otherwise).
+ * QoI of eq. (PCE_u) statistics: q_a = w_S . U_a with w_S the exact
  * integration weights of S = [1/4, 3/4]^2 divided by |S|, and
  * J = q_0 + sum_{a>0} q_a^2 (mean plus variance of the subdomain mean).
  * U: device doubles.  q: host, P doubles (may be NULL).  J: host. */
 int sg_qoi(sg_ctx* ctx, const double* U, double* q, double* J);
 
-/* Adjoint gradient of J at the solution U: solves A lambda = dJ/dU with the
+/* SG_DISC_Q1 only (SG_EINVAL otherwise).
+ * Adjoint gradient of J at the solution U: solves A lambda = dJ/dU with the
  * same solver options, then dJ/dc_{k,e} = -sum G_k(a,b) lambda_{a,e}^T K_ref U_{b,e}
  * and the chain rule to sigma, the KL amplitudes s_k and the interior nodal
  * values of a0.  U: device doubles (a converged solution).  Outputs host:
@@ -173,7 +196,7 @@ int sg_qoi_grad(sg_ctx* ctx, const double* U, const sg_solve_opts* opts, double*
 
 /* Host-only run of the setup arithmetic of sg_setup, without any device:
  * for checking the tables on machines without a GPU.  Outputs (host, each may
- * be NULL): cell_coeffs (m+1)*n*n as sg_get_cell_coeffs; fine_stencil N*9 and
+ * be NULL): cell_coeffs as sg_get_cell_coeffs; fine_stencil N*9 and
  * level1_stencil N_1*9 (9-point rows of K_0 and of its first Galerkin coarse
  * operator, (dy,dx) row-major, N_1 = (n/2-1)^2, left untouched when the fine
  * grid is the coarsest); coarsest_inverse Nc*Nc (row-major inverse of the

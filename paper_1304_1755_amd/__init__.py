@@ -21,6 +21,8 @@ SG_OK, SG_WNOTCOERCIVE = 0, 1
 SG_EINVAL, SG_ENOMEM, SG_EHIP, SG_ENOTCONV, SG_ENAN = -1, -2, -3, -4, -5
 SG_F64, SG_F32, SG_MIXED = 0, 1, 2
 SG_COLOUR_FOUR, SG_COLOUR_RB = 0, 1
+SG_DISC_Q1, SG_DISC_P1 = 0, 1
+DISCRETIZATIONS = {"q1": SG_DISC_Q1, "p1": SG_DISC_P1}
 
 EXPORTED = ["sg_setup", "sg_query", "sg_get_cell_coeffs", "sg_rhs", "sg_apply", "sg_residual", "sg_vcycle",
             "sg_precond_diag", "sg_precond_tri", "sg_precond_sym", "sg_solve", "sg_qoi", "sg_qoi_grad", "sg_setup_host", "sg_sync",
@@ -30,7 +32,8 @@ EXPORTED = ["sg_setup", "sg_query", "sg_get_cell_coeffs", "sg_rhs", "sg_apply", 
 class Options(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int), ("m", ctypes.c_int), ("p", ctypes.c_int),
                 ("sigma", ctypes.c_double), ("corr_len", ctypes.c_double), ("colour_mode", ctypes.c_int),
-                ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("coarsest_cells", ctypes.c_int)]
+                ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("coarsest_cells", ctypes.c_int),
+                ("discretization", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -119,31 +122,41 @@ def solve_options(solver="fgmres", precond="tri", prec=SG_F64, restart=30, max_i
                      restart=restart, max_it=max_it, rtol=rtol, use_x0=int(use_x0), timing=int(timing))
 
 
-def setup_host(n, m, p, sigma, corr_len=0.5, a0_nodal=None, kl_amp=None, coarsest=8):
-    """Run the library's host-side setup only (no device) and return its tables."""
+def setup_host(n, m, p, sigma, corr_len=0.5, a0_nodal=None, kl_amp=None, coarsest=8, disc="q1"):
+    """Run the library's host-side setup only (no device) and return its tables.
+
+    disc "q1": bilinear elements, f = 1; "p1": the triangulation, load and
+    variance-one law of Sec. 6 (cell rows then hold the 2 n^2 triangles).
+    """
     import numpy as np
     lib = load_library()
     opt = Options(n_cells=n, m=m, p=p, sigma=sigma, corr_len=corr_len, colour_mode=0, nu1=2, nu2=2,
-                  coarsest_cells=coarsest)
+                  coarsest_cells=coarsest, discretization=DISCRETIZATIONS[disc])
+    nel = n * n * (2 if disc == "p1" else 1)
     a0k, a0p = _dptr(a0_nodal) if a0_nodal is not None else (None, None)
     ak, ap = _dptr(kl_amp) if kl_amp is not None else (None, None)
     N, N1, Nc = (n - 1) ** 2, (n // 2 - 1) ** 2, (coarsest - 1) ** 2
-    out = dict(cell=np.empty((m + 1) * n * n), fine=np.empty(N * 9), l1=np.full(max(N1, 1) * 9, np.nan),
+    out = dict(cell=np.empty((m + 1) * nel), fine=np.empty(N * 9), l1=np.full(max(N1, 1) * 9, np.nan),
                cinv=np.empty(Nc * Nc), lam=np.empty(max(m, 1)), amin=np.empty(1))
     P = ctypes.POINTER(ctypes.c_double)
     code = lib.sg_setup_host(ctypes.byref(opt), a0p, ap, *[out[k].ctypes.data_as(P) for k in
                                                            ("cell", "fine", "l1", "cinv", "lam", "amin")])
     _check(code, allow=(SG_OK, SG_WNOTCOERCIVE))
-    return dict(cell=out["cell"].reshape(m + 1, n * n), fine=out["fine"].reshape(N, 9),
+    return dict(cell=out["cell"].reshape(m + 1, nel), fine=out["fine"].reshape(N, 9),
                 l1=out["l1"][:N1 * 9].reshape(N1, 9), cinv=out["cinv"].reshape(Nc, Nc), lam=out["lam"][:m],
                 a_min_h=float(out["amin"][0]), code=code)
 
 
 class Problem:
-    """One stochastic Galerkin system A = sum_k G_k (x) K_k on the current HIP device."""
+    """One stochastic Galerkin system A = sum_k G_k (x) K_k on the current HIP device.
+
+    disc "q1": bilinear elements on the unit square with f = 1; "p1": the
+    setting of Sec. 6 (linear elements, f = 2 (1/2 - x^2 - y^2), unit-variance
+    uniform xi_k; pass corr_len=1.0 for the paper's L).
+    """
 
     def __init__(self, n, m, p, sigma, corr_len=0.5, a0_nodal=None, kl_amp=None, colour="four", nu1=2, nu2=2,
-                 coarsest=8, stream=None):
+                 coarsest=8, stream=None, disc="q1"):
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("libsgbt needs a HIP device")
@@ -151,7 +164,7 @@ class Problem:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = Options(n_cells=n, m=m, p=p, sigma=sigma, corr_len=corr_len,
                       colour_mode={"four": SG_COLOUR_FOUR, "rb": SG_COLOUR_RB}[colour], nu1=nu1, nu2=nu2,
-                      coarsest_cells=coarsest)
+                      coarsest_cells=coarsest, discretization=DISCRETIZATIONS[disc])
         a0p = amp = None
         a0_keep = amp_keep = None
         if a0_nodal is not None:
@@ -164,7 +177,7 @@ class Problem:
         self.warning = _check(lib.sg_setup(ctypes.byref(opt), a0p, amp, ctypes.c_void_p(self.stream.cuda_stream),
                                            ctypes.byref(ctx)), allow=(SG_OK, SG_WNOTCOERCIVE))
         self._ctx = ctx
-        self.n, self.m, self.p, self.sigma = n, m, p, sigma
+        self.n, self.m, self.p, self.sigma, self.disc = n, m, p, sigma, disc
         Nv, Pv = ctypes.c_int(), ctypes.c_int()
         offs = (ctypes.c_int * (p + 2))()
         mi = (ctypes.c_int * max(1, 256 * max(m, 1)))()
@@ -190,9 +203,10 @@ class Problem:
 
     def cell_coeffs(self):
         import numpy as np
-        out = np.empty((self.m + 1) * self.n * self.n)
+        nel = self.n * self.n * (2 if self.disc == "p1" else 1)
+        out = np.empty((self.m + 1) * nel)
         _check(load_library().sg_get_cell_coeffs(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-        return out.reshape(self.m + 1, self.n * self.n)
+        return out.reshape(self.m + 1, nel)
 
     # -- hot path
     def rhs(self, F=None):

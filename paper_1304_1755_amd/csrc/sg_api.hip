@@ -621,8 +621,13 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
     if (n < 4 || n > 4096 || n % 4 != 0 || opt->m < 0 || opt->m > kMaxM || opt->p < 0 || opt->p > 8 || nc < 2 ||
         nc > n || n % nc != 0 || ((n / nc) & (n / nc - 1)) != 0 || (nc - 1) * (nc - 1) > 4096 ||
         !(opt->corr_len > 0.0) || opt->nu1 < 0 || opt->nu1 > 8 || opt->nu2 < 0 || opt->nu2 > 8 ||
-        (opt->colour_mode != SG_COLOUR_FOUR && opt->colour_mode != SG_COLOUR_RB) || !std::isfinite(opt->sigma)) {
+        (opt->colour_mode != SG_COLOUR_FOUR && opt->colour_mode != SG_COLOUR_RB) || !std::isfinite(opt->sigma) ||
+        (opt->discretization != SG_DISC_Q1 && opt->discretization != SG_DISC_P1)) {
         set_error("sg_setup: invalid options (need n % 4 == 0, n = coarsest * 2^L, m <= 8, p <= 8, ...)");
+        return SG_EINVAL;
+    }
+    if (opt->discretization == SG_DISC_P1 && (a0_nodal || opt->colour_mode != SG_COLOUR_FOUR)) {
+        set_error("sg_setup: SG_DISC_P1 takes a0 = 1 (a0_nodal NULL) and SG_COLOUR_FOUR");
         return SG_EINVAL;
     }
     {
@@ -655,14 +660,16 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
     const int m = hs.m, P = hs.P;
     const size_t ncell = (size_t)n * n;
     {
-        std::vector<double> cm(ncell * (m + 1)), kl(ncell * std::max(m, 1));
-        for (size_t e = 0; e < ncell; ++e) {
-            for (int k = 0; k <= m; ++k) cm[e * (m + 1) + k] = hs.cellc[(size_t)k * ncell + e] / 6.0;
-            for (int k = 0; k < m; ++k) kl[e * m + k] = hs.klcell[(size_t)k * ncell + e];
-        }
-        if ((rc = upload(c, &c->cell64, cm))) return fail(rc);
+        if ((rc = upload(c, &c->cell64, hs.kcoef))) return fail(rc);
         if ((rc = upload(c, &c->zeros, std::vector<double>(256, 0.0)))) return fail(rc);
-        if ((rc = upload(c, &c->klcell, kl))) return fail(rc);
+        if (hs.disc == SG_DISC_Q1) {
+            std::vector<double> kl(ncell * std::max(m, 1));
+            for (size_t e = 0; e < ncell; ++e)
+                for (int k = 0; k < m; ++k) kl[e * m + k] = hs.klcell[(size_t)k * ncell + e];
+            if ((rc = upload(c, &c->klcell, kl))) return fail(rc);
+        } else if ((rc = upload(c, &c->load, hs.load))) {
+            return fail(rc);
+        }
     }
     if ((rc = upload(c, &c->kinv, hs.coarse_inv))) return fail(rc);
     c->levels.resize(hs.mg_n.size());
@@ -736,6 +743,14 @@ int sg_rhs(sg_ctx* c, double* F) {
     if (!c || !F) {
         set_error("sg_rhs: null argument");
         return SG_EINVAL;
+    }
+    if (c->hs.disc == SG_DISC_P1) {
+        // column 0 of the node-major block is the precomputed load vector
+        const size_t P = c->hs.P;
+        SG_HIP_CHECK(hipMemsetAsync(F, 0, (size_t)c->hs.N * P * sizeof(double), c->stream));
+        SG_HIP_CHECK(hipMemcpy2DAsync(F, P * sizeof(double), c->load, sizeof(double), sizeof(double), c->hs.N,
+                                      hipMemcpyDeviceToDevice, c->stream));
+        return SG_OK;
     }
     const double h = 1.0 / c->hs.n;
     SG_HIP_CHECK(vec_rhs(c->stream, F, c->hs.N, c->hs.P, h * h));
@@ -830,8 +845,8 @@ int sg_solve(sg_ctx* c, const double* F, double* U, const sg_solve_opts* opts, s
 }
 
 int sg_qoi(sg_ctx* c, const double* U, double* q, double* J) {
-    if (!c || !U || !J) {
-        set_error("sg_qoi: null argument");
+    if (!c || !U || !J || c->hs.disc != SG_DISC_Q1) {
+        set_error("sg_qoi: null argument or a discretisation other than SG_DISC_Q1");
         return SG_EINVAL;
     }
     int rc = ensure_scalars(c);
@@ -850,7 +865,8 @@ int sg_qoi(sg_ctx* c, const double* U, double* q, double* J) {
 
 int sg_qoi_grad(sg_ctx* c, const double* U, const sg_solve_opts* opts, double* J, double* dJ_dsigma, double* dJ_damp,
                 double* dJ_da0, sg_solve_info* adj_info) {
-    if (!c || !U || !J || !dJ_dsigma || (!dJ_damp && c->hs.m) || !dJ_da0 || check_opts(c, opts) != SG_OK) {
+    if (!c || !U || !J || !dJ_dsigma || (!dJ_damp && c->hs.m) || !dJ_da0 || c->hs.disc != SG_DISC_Q1 ||
+        check_opts(c, opts) != SG_OK) {
         set_error("sg_qoi_grad: invalid argument");
         return SG_EINVAL;
     }
@@ -888,7 +904,9 @@ int sg_setup_host(const sg_options* opt, const double* a0_nodal, const double* k
                   double* a_min_h) {
     if (!opt || opt->n_cells < 4 || opt->n_cells > 4096 || opt->n_cells % 4 || opt->m < 0 || opt->m > kMaxM ||
         opt->p < 0 || opt->p > 8 || opt->coarsest_cells < 2 || opt->coarsest_cells > opt->n_cells ||
-        opt->n_cells % opt->coarsest_cells || !(opt->corr_len > 0.0)) {
+        opt->n_cells % opt->coarsest_cells || !(opt->corr_len > 0.0) ||
+        (opt->discretization != SG_DISC_Q1 && opt->discretization != SG_DISC_P1) ||
+        (opt->discretization == SG_DISC_P1 && a0_nodal)) {
         set_error("sg_setup_host: invalid options");
         return SG_EINVAL;
     }

@@ -1,296 +1,14 @@
-// Matrix-free stochastic Galerkin operator (Sec. 3.1, eq. (tensor-product)):
-//
-//     Y = sum_{k=0..m} K_k U G_k^T        (U, Y: N x P node-major)
-//
-// and its two relatives that share the same kernel:
-//   * the true residual  Y = R - A U;
-//   * the lower coupling of the block-triangular sweep (Sec. 4.2):
-//       Y_d = R_d - sum_{k>=1} [G_k]_{d,d-1} (x) K_k U_{d-1}.
-//
-// Design (gfx950): one workgroup walks a segment of one grid row, one node
-// per step; its lanes (64 per wave, up to 4 waves) hold the P chaos modes of
-// that node, so every load of a node's mode vector is a contiguous, coalesced
-// access and the cell coefficients c_{k,e} of the four cells around the node
-// are wave-uniform scalars, loaded once and reused by all modes.
-// With cell-constant coefficients, K_k u at a node is sum over the four cells
-// of c_{k,e} r_e, where r_e = 4u_c - (two edge neighbours in that cell)
-// - 2 (opposite corner) is the node's row of the Q1 element matrix (times 6;
-// the 1/6 is folded into the coefficients).  r_e is computed once per mode
-// and shared by all m+1 stencils.  The G_k coupling (alpha <-> alpha +- e_k,
-// Sec. 3.2) crosses lanes: each lane writes its K_k u (k >= 1) to an LDS
-// exchange buffer and reads back the entries of its coupling partners through
-// precomputed index/coefficient tables held in registers.  A 3x3 window of
-// mode vectors slides along the row, so each step loads one new column.
+// The stochastic Galerkin operator for bilinear elements, and the dispatch
+// over the discretisations (the kernel is in sg_apply_kernel.h).
 
-#include <type_traits>
-#include <utility>
-
-#include "sg_internal.h"
+#include "sg_apply_kernel.h"
 
 namespace sg {
 
-namespace {
-
-template <typename T>
-__device__ __forceinline__ double ld_as_double(const T* p) { return (double)(*p); }
-
-template <typename T>
-__device__ __forceinline__ void st_from_double(T* p, double v) { *p = (T)v; }
-
-__device__ __forceinline__ int remap_block_xcd(int b, int nb) {
-    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of logical blocks so neighbouring grid rows share an L2
-    const int x = b & 7, i = b >> 3;
-    const int q = nb >> 3, r = nb & 7;
-    return x * q + (x < r ? x : r) + i;
-}
-
-constexpr int kApplyRows = 2;  // grid rows per workgroup
-
-template <typename F, int... J>
-__device__ __forceinline__ void unroll_steps(F&& f, std::integer_sequence<int, J...>) {
-    (f(std::integral_constant<int, J>{}), ...);
-}
-
-// One workgroup per segment of RW grid rows (a row pair for RW = 2); wave s
-// of the workgroup owns modes [64 s, 64 s + 64) of every node in the
-// segment.  Per column, every wave writes the K_k u (k >= 1) of its RW nodes
-// into a block-shared LDS exchange buffer, the workgroup meets at a barrier,
-// and every wave then gathers its coupling partners from the whole buffer.
-// Splitting the modes over waves keeps each wave's coupling tables and
-// window small, so several workgroups share a CU and hide memory latency;
-// two rows per workgroup share the window's middle rows and the cell row
-// between them, and halve the synchronizations per node.
-template <int M, int NS, int RW, typename Tin, typename Tout, bool HAS_R>
-__global__ void __launch_bounds__(NS * 64)
-k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int ldr,
-           Tout* __restrict__ Y, int ldy, const double* __restrict__ cell,
-           const uint32_t* __restrict__ toff, const double* __restrict__ tcoef, int n, int W_in,
-           int W_out, int self, const Tin* __restrict__ zin, int seg, int nseg) {
-    constexpr int MM = M > 0 ? M : 1;
-    constexpr int LANES = NS * 64;
-    constexpr int NODE = MM * LANES + 2;      // exchange entries of one node (+ its zero entry)
-    constexpr int NBUF = RW == 1 ? 2 : 1;      // one row: double-buffered by column parity
-    __shared__ double S[NBUF][RW * NODE];
-    const int lane = threadIdx.x & 63;
-    const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wave's slot (uniform)
-    const int nx = n - 1;
-    const int lb = remap_block_xcd(blockIdx.x, gridDim.x);
-    const int nrb = (nx + RW - 1) / RW;
-    if (lb >= nrb * nseg) return;  // whole block
-    // segment-major: the row blocks of one column segment are consecutive, so
-    // the workgroups that share a halo row run at the same time on one XCD
-    const int sgi = lb / nrb;
-    const int yb = lb - sgi * nrb;
-    const int y0 = yb * RW;
-    const int x0 = sgi * seg;
-    const int x1 = min(x0 + seg, nx);
-    const int t = s * 64 + lane;
-    const bool has_out = s * 64 < W_out;  // uniform
-    const bool vin = t < W_in, vout = t < W_out;
-
-    // this lane's partners: position 2k = alpha + e_k, 2k+1 = alpha - e_k
-    uint32_t off[MM];
-    double ce[2 * MM];
-#pragma unroll
-    for (int j = 0; j < MM; ++j) {
-        off[j] = M > 0 ? toff[t * MM + j] : 0u;
-        ce[2 * j] = M > 0 ? tcoef[t * 2 * MM + 2 * j] : 0.0;
-        ce[2 * j + 1] = M > 0 ? tcoef[t * 2 * MM + 2 * j + 1] : 0.0;
-    }
-    if (threadIdx.x < RW * NBUF) S[threadIdx.x / RW][(threadIdx.x % RW) * NODE + MM * LANES] = 0.0;  // zero entries
-
-    // Circular window wb[row][c] of mode vectors, rows y0-1 .. y0+RW: column
-    // x of the grid lives in wb[.][(x - x0 + 1) mod C].  Step x reads columns
-    // x-1, x, x+1 and issues the loads of column x+1+D, so D columns are in
-    // flight while earlier steps compute; the walk is unrolled by C, which
-    // makes every column role, the R slot and the LDS buffer parity a
-    // compile-time constant and the window needs no register moves.  A
-    // neighbour outside the grid is read from the zero vector zin (a
-    // wave-uniform choice of base pointer, so no per-value select), and lanes
-    // past W_in read a valid column: their values feed no partner.
-    constexpr int C = RW == 1 ? 8 : 6;
-    constexpr int D = C - 3;  // columns in flight; D + 3 columns are live
-    constexpr int NR = RW + 2;
-    const uint32_t tci = vin ? t : W_in - 1;
-    const uint32_t tco = vout ? t : W_out - 1;
-    Tin wb[NR][C];
-    double qr[RW][D];  // R at (x, y0 + q) lives in qr[q][(x - x0) mod D]
-    auto load_col = [&](int c, int xc) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int yy = y0 + r - 1;
-            const bool inside = yy >= 0 && yy < nx && xc >= 0 && xc < nx;  // uniform
-            const Tin* rowp = inside ? U + ((size_t)yy * nx + xc) * ldu : zin;
-            wb[r][c] = rowp[tci];
-        }
-    };
-    auto load_r = [&](int c, int x) {
-        if (HAS_R) {
-#pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                const int yq = min(y0 + q, nx - 1);
-                qr[q][c % D] = R[((size_t)yq * nx + min(x, nx - 1)) * ldr + tco];
-            }
-        }
-    };
-    // columns x0-1 .. x0+D and R at x0 .. x0+D-1
-    load_col(0, x0 - 1);
-    load_col(1, x0);
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        load_col(2 + i, x0 + 1 + i);
-        load_r(i, x0 + i);
-    }
-
-    auto step = [&](auto kstep, int x) {
-        constexpr int j = decltype(kstep)::value;  // x - x0 mod C
-        constexpr int cW = j % C, cC = (j + 1) % C, cE = (j + 2) % C, cL = (j + 2 + D) % C;
-        double* B = S[NBUF == 2 ? (j & 1) : 0];
-        double rv[RW];
-#pragma unroll
-        for (int q = 0; q < RW; ++q) rv[q] = HAS_R ? qr[q][j % D] : 0.0;
-        load_col(cL, x + 1 + D);  // past the segment: zero-vector or in-grid loads, harmless
-        load_r(j, x + D);         // the slot just read
-        double s0[RW];
-#pragma unroll
-        for (int q = 0; q < RW; ++q) {
-            s0[q] = 0.0;
-            if (RW > 1 && y0 + q >= nx) break;  // uniform: no such row (its cells would lie outside)
-            // node (x, y0 + q); cells SW (x, y0+q), SE (x+1, y0+q), NW (x, y0+q+1), NE (x+1, y0+q+1)
-            const double wSW = (double)wb[q][cW], wS = (double)wb[q][cC], wSE = (double)wb[q][cE];
-            const double wW = (double)wb[q + 1][cW], wc = (double)wb[q + 1][cC], wE = (double)wb[q + 1][cE];
-            const double wNW = (double)wb[q + 2][cW], wN = (double)wb[q + 2][cC], wNE = (double)wb[q + 2][cE];
-            const double* cSW = cell + ((size_t)(y0 + q) * n + x) * (M + 1);
-            const double* cSE = cSW + (M + 1);
-            const double* cNW = cell + ((size_t)(y0 + q + 1) * n + x) * (M + 1);
-            const double* cNE = cNW + (M + 1);
-            const double uc4 = 4.0 * wc;
-            const double rSW = fma(-2.0, wSW, uc4 - (wS + wW));
-            const double rSE = fma(-2.0, wSE, uc4 - (wS + wE));
-            const double rNW = fma(-2.0, wNW, uc4 - (wN + wW));
-            const double rNE = fma(-2.0, wNE, uc4 - (wN + wE));
-            s0[q] = fma(cSW[0], rSW, fma(cSE[0], rSE, fma(cNW[0], rNW, cNE[0] * rNE)));
-#pragma unroll
-            for (int kk = 1; kk <= M; ++kk)
-                B[q * NODE + (kk - 1) * LANES + t] =
-                    fma(cSW[kk], rSW, fma(cSE[kk], rSE, fma(cNW[kk], rNW, cNE[kk] * rNE)));
-        }
-        // LDS writes done, then the block barrier (no global-memory wait: the
-        // window loads stay in flight)
-        __builtin_amdgcn_s_waitcnt(0xC07F);
-        __asm__ __volatile__("" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        __asm__ __volatile__("" ::: "memory");
-        if (has_out) {
-#pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                if (RW > 1 && y0 + q >= nx) break;  // uniform: the last row pair of an odd grid
-                const double* Bq = B + q * NODE;
-                double acc = self ? s0[q] : 0.0;
-#pragma unroll
-                for (int jj = 0; jj < M; ++jj) {
-                    // absent partners read the node's zero entry: unconditional
-                    // gathers schedule better than skipping positions per wave
-                    acc = fma(ce[2 * jj], Bq[off[jj] & 0xFFFFu], acc);
-                    acc = fma(ce[2 * jj + 1], Bq[off[jj] >> 16], acc);
-                }
-                if (vout) {
-                    const size_t node = (size_t)(y0 + q) * nx + x;
-                    st_from_double(Y + node * ldy + t, HAS_R ? rv[q] - acc : acc);
-                }
-            }
-        }
-        if (NBUF == 1) {
-            // single buffer: every wave has gathered before the next column is written
-            __builtin_amdgcn_s_waitcnt(0xC07F);
-            __asm__ __volatile__("" ::: "memory");
-            __builtin_amdgcn_s_barrier();
-            __asm__ __volatile__("" ::: "memory");
-        }
-    };
-    for (int x = x0; x < x1; x += C) {
-        // x, x1 are uniform, so every wave of the block meets the same barriers
-        unroll_steps(
-            [&](auto kj) {
-                constexpr int j = decltype(kj)::value;
-                if (j == 0 || x + j < x1) step(kj, x + j);
-            },
-            std::make_integer_sequence<int, C>{});
-    }
-}
-
-template <typename Tin, typename Tout, int M, int NS>
-hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
-                    int ldy, const double* cell, int n, const void* zin) {
-    constexpr int RW = kApplyRows;
-    const int nx = n - 1;
-    const int seg = 32;
-    const int nseg = (nx + seg - 1) / seg;
-    const int blocks = (nx + RW - 1) / RW * nseg;
-    if (R)
-        hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, true>), dim3(blocks), dim3(NS * 64), 0, st,
-                           (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out,
-                           pl.self, (const Tin*)zin, seg, nseg);
-    else
-        hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, false>), dim3(blocks), dim3(NS * 64), 0, st,
-                           (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out,
-                           pl.self, (const Tin*)zin, seg, nseg);
-    return hipGetLastError();
-}
-
-template <typename Tin, typename Tout, int M>
-hipError_t launch_ns(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
-                     int ldy, const double* cell, int n, const void* zin) {
-    switch (pl.nslot) {
-        case 1: return launch_t<Tin, Tout, M, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 2: return launch_t<Tin, Tout, M, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 3: return launch_t<Tin, Tout, M, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 4: return launch_t<Tin, Tout, M, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <typename Tin, typename Tout>
-hipError_t launch_m(hipStream_t st, int m, const Plan& pl, const void* U, int ldu, const double* R, int ldr,
-                    void* Y, int ldy, const double* cell, int n, const void* zin) {
-    switch (m) {
-        case 0: return launch_ns<Tin, Tout, 0>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 1: return launch_ns<Tin, Tout, 1>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 2: return launch_ns<Tin, Tout, 2>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 3: return launch_ns<Tin, Tout, 3>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 4: return launch_ns<Tin, Tout, 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 5: return launch_ns<Tin, Tout, 5>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 6: return launch_ns<Tin, Tout, 6>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 7: return launch_ns<Tin, Tout, 7>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 8: return launch_ns<Tin, Tout, 8>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-    }
-    return hipErrorInvalidValue;
-}
-
-}  // namespace
-
 int launch_apply(sg_ctx* c, const Plan& pl, const void* U, int in_float, const double* R, void* Y, int out_float,
                  int ldu, int ldy, int ldr) {
-    hipError_t e;
-    const int m = c->hs.m, n = c->hs.n;
-    // Y = R - A U, or Y = A U when R is null; c->zeros serves as the zero neighbour
-    const void* zin = c->zeros;
-    if (!in_float && !out_float)
-        e = launch_m<double, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, zin);
-    else if (in_float && !out_float)
-        e = launch_m<float, double>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, zin);
-    else if (in_float && out_float)
-        e = launch_m<float, float>(c->stream, m, pl, U, ldu, R, ldr, Y, ldy, c->cell64, n, zin);
-    else {
-        set_error("apply: double input with float output is not provided");
-        return SG_EINVAL;
-    }
-    if (e != hipSuccess) {
-        set_error(std::string("apply launch: ") + hipGetErrorString(e));
-        return SG_EHIP;
-    }
-    return SG_OK;
+    if (c->hs.disc == SG_DISC_P1) return launch_apply_p1(c, pl, U, in_float, R, Y, out_float, ldu, ldy, ldr);
+    return launch_apply_disc<false>(c, pl, U, in_float, R, Y, out_float, ldu, ldy, ldr);
 }
 
 }  // namespace sg

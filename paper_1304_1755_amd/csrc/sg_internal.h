@@ -29,12 +29,20 @@ void set_error(const std::string& msg);
 // ---------------------------------------------------------------- host setup
 struct HostSetup {
     int n = 0, m = 0, p = 0, P = 0, N = 0;
+    int disc = SG_DISC_Q1;             // discretisation
+    double gscale = 1.0;               // factor on the G_k (k >= 1) coupling entries: sqrt 3 for SG_DISC_P1
     std::vector<int> offsets;          // p+2
     std::vector<int> midx;             // P*m
     std::vector<double> lambda;        // m eigenvalues lambda_k of the 2-D modes
     std::vector<double> amps;          // m amplitudes s_k
-    std::vector<double> cellc;         // (m+1) x n*n, row k
-    std::vector<double> klcell;        // m x n*n values b_k at cell centres
+    std::vector<double> cellc;         // (m+1) x n_elem, row k (n_elem = n*n cells, or 2 n*n triangles)
+    std::vector<double> klcell;        // m x n*n values b_k at cell centres (SG_DISC_Q1)
+    // operator coefficients in the apply kernel's layout, n*n positions (cx, cy) at cy*n + cx:
+    //   SG_DISC_Q1: (m+1) values c_{k,cell} / 6 per cell;
+    //   SG_DISC_P1: 2(m+1) values per grid vertex (cx, cy): the weights of its east edge
+    //   (to (cx+1, cy)) for k = 0..m, then those of its north edge (to (cx, cy+1))
+    std::vector<double> kcoef;
+    std::vector<double> load;          // N: f_h (SG_DISC_P1; f = 1 is generated on the device)
     double a_min_h = 0.0;
     // multigrid, level 0 = finest
     std::vector<int> mg_n;             // cells per side per level
@@ -107,7 +115,8 @@ struct sg_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     // device data
-    double* cell64 = nullptr;   // n*n x (m+1), cell-major, pre-scaled by 1/6
+    double* cell64 = nullptr;   // HostSetup::kcoef on the device
+    double* load = nullptr;     // HostSetup::load on the device (SG_DISC_P1)
     double* klcell = nullptr;   // n*n x m  b_k at cell centres, cell-major
     double* kinv = nullptr;     // N_c x N_c
     double* zeros = nullptr;    // 256 zeros: the value of grid neighbours outside the domain in the apply
@@ -126,6 +135,9 @@ namespace sg {
 // output mode (Y may also be a compact buffer of width W_out).
 int launch_apply(sg_ctx* c, const Plan& pl, const void* U, int in_float, const double* R, void* Y,
                  int out_float, int ldu, int ldy, int ldr);
+// the same for SG_DISC_P1 (called by launch_apply)
+int launch_apply_p1(sg_ctx* c, const Plan& pl, const void* U, int in_float, const double* R, void* Y,
+                    int out_float, int ldu, int ldy, int ldr);
 int launch_vcycle(sg_ctx* c, const void* f, int ldf, void* u, int ldu, int width, int is_float);
 int launch_cast(hipStream_t s, const void* src, int src_float, int lds, void* dst, int dst_float, int ldd,
                 int rows, int width);

@@ -11,9 +11,12 @@
 //
 // Components: multi-colour Gauss-Seidel (four colours (I mod 2, J mod 2), or
 // red/black with each colour updated from its start-of-colour values),
-// residual, full-weighting restriction R = P^T, bilinear prolongation P, and
-// the coarsest grid solved with the explicit inverse of its operator in
-// double precision.
+// residual, restriction R = P^T, prolongation P, and the coarsest grid
+// solved with the explicit inverse of its operator in double precision.  P is
+// the bilinear interpolation for Q1 elements, or the linear interpolation of
+// the triangulation of Sec. 6 (its diagonals run south-west to north-east)
+// for P1 elements: the two agree on the grid lines, and a fine cell centre
+// takes the mean of the coarse SW and NE corners instead of all four.
 //
 // Kernel forms by block width W (modes) and grid size:
 //   * four-colour smoothing runs as row phases (one launch per row parity,
@@ -53,6 +56,60 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     const int x = b & 7, i = b >> 3;
     const int q = nb >> 3, r = nb & 7;
     return x * q + (x < r ? x : r) + i;
+}
+
+// Weight of a coarse node in the interpolated value at a fine node offset by
+// (dx, dy) from the coarse node's own fine position (|dx|, |dy| <= 1).
+template <typename T>
+__device__ __forceinline__ T transfer_w(int dx, int dy, bool p1) {
+    if (dx != 0 && dy != 0) return p1 ? (dx == dy ? T(0.5) : T(0)) : T(0.25);
+    return (dx == 0 ? T(1) : T(0.5)) * (dy == 0 ? T(1) : T(0.5));
+}
+
+// (P^T r) at coarse node (X, Y): get(x, y) reads the fine residual at fine node (x, y)
+template <typename T, typename G>
+__device__ __forceinline__ T restrict_value(G get, int X, int Y, bool p1) {
+    const int fx = 2 * X + 1, fy = 2 * Y + 1;
+    T acc = T(0);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const T w = transfer_w<T>(dx, dy, p1);
+            if (w != T(0)) acc += w * get(fx + dx, fy + dy);
+        }
+    return acc;
+}
+
+// (P e)(x, y) at fine node (x, y): get(X, Y) reads the coarse correction at
+// coarse node (X, Y), nxc coarse nodes per side (zero outside)
+template <typename T, typename G>
+__device__ __forceinline__ T prolong_value(G get, int nxc, int x, int y, bool p1) {
+    if (p1 && !(x & 1) && !(y & 1)) {
+        // a fine cell centre: on the diagonal from the coarse SW to NE corner
+        const int cx0 = (x >> 1) - 1, cy0 = (y >> 1) - 1, cx1 = x >> 1, cy1 = y >> 1;
+        T a = T(0);
+        if (cx0 >= 0 && cy0 >= 0) a += get(cx0, cy0);
+        if (cx1 < nxc && cy1 < nxc) a += get(cx1, cy1);
+        return T(0.5) * a;
+    }
+    // fine x odd: on coarse column (x-1)/2; x even: between x/2-1 and x/2
+    int cx0, cx1, cy0, cy1;
+    T wx, wy;
+    if (x & 1) { cx0 = cx1 = (x - 1) >> 1; wx = T(1); } else { cx0 = (x >> 1) - 1; cx1 = x >> 1; wx = T(0.5); }
+    if (y & 1) { cy0 = cy1 = (y - 1) >> 1; wy = T(1); } else { cy0 = (y >> 1) - 1; cy1 = y >> 1; wy = T(0.5); }
+    T acc = T(0);
+    const int ncx = (cx0 == cx1) ? 1 : 2, ncy = (cy0 == cy1) ? 1 : 2;
+    for (int b = 0; b < ncy; ++b) {
+        const int cy = b ? cy1 : cy0;
+        if (cy < 0 || cy >= nxc) continue;
+        for (int a = 0; a < ncx; ++a) {
+            const int cx = a ? cx1 : cx0;
+            if (cx < 0 || cx >= nxc) continue;
+            acc += get(cx, cy);
+        }
+    }
+    return wx * wy * acc;
 }
 
 template <typename T>
@@ -169,34 +226,28 @@ __global__ void k_residual(const T* __restrict__ sten, const T* __restrict__ u, 
     r[(size_t)node * ldr + mode] = acc;
 }
 
-// coarse node (X, Y) sits on fine node (2X+1, 2Y+1); weights 1, 1/2, 1/4
+// coarse node (X, Y) sits on fine node (2X+1, 2Y+1)
 template <typename T>
-__global__ void k_restrict(const T* __restrict__ r, int ldr, T* __restrict__ fc, int ldc, int nxc, int width) {
+__global__ void k_restrict(const T* __restrict__ r, int ldr, T* __restrict__ fc, int ldc, int nxc, int width,
+                           int p1) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
     const int node = xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
     if (mode >= width || node >= nxc * nxc) return;
     const int Y = node / nxc, X = node - Y * nxc;
     const int nxf = 2 * nxc + 1;
-    const int fx = 2 * X + 1, fy = 2 * Y + 1;
-    T acc = T(0);
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-        const T wy = dy == 0 ? T(1) : T(0.5);
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-            const T wx = dx == 0 ? T(1) : T(0.5);
-            acc += wx * wy * r[((size_t)(fy + dy) * nxf + (fx + dx)) * ldr + mode];
-        }
-    }
-    fc[(size_t)node * ldc + mode] = acc;
+    auto get = [&](int x, int y) { return r[((size_t)y * nxf + x) * ldr + mode]; };
+    fc[(size_t)node * ldc + mode] = restrict_value<T>(get, X, Y, p1 != 0);
 }
 
 // Residual and restriction in one pass for wide blocks (W >= 16 modes):
 // fc = R (f - K u) without storing the fine residual.  A workgroup walks a
 // segment of kRrSeg nodes of one coarse row Y; lanes are modes.  Per coarse
-// column X it forms the row-weighted fine residual c(x) = r(x, fy-1)/2 +
-// r(x, fy) + r(x, fy+1)/2 (fy = 2Y+1) at x = 2X+1 and 2X+2, from a window
-// of five fine rows of u, and then fc(X) = c(2X)/2 + c(2X+1) + c(2X+2)/2.
+// column X it forms the fine residual of the three rows fy-1, fy, fy+1
+// (fy = 2Y+1) at columns x = 2X+1 and 2X+2, from a window of five fine rows
+// of u.  Bilinear transfer: with c(x) = r(x, fy-1)/2 + r(x, fy) + r(x, fy+1)/2,
+// fc(X) = c(2X)/2 + c(2X+1) + c(2X+2)/2.  P1 transfer (P1T): the centre
+// column weighs the rows as c does, the west column takes (r(fy-1) + r(fy))/2
+// and the east column (r(fy) + r(fy+1))/2.
 // Loads are clamped into the grid (zero outside) and issued a ring of steps
 // ahead; the stencils of the three fine rows are staged in LDS.
 constexpr int kRrSeg = 16;       // coarse nodes per segment on the fine levels
@@ -204,7 +255,7 @@ constexpr int kRrSegShort = 4;   // on coarse levels, where long walks leave too
 // narrowest block the walking transfer kernels take (narrower: one node per thread)
 constexpr int kWalkMinWidth = 16;
 
-template <typename T, int SEG>
+template <typename T, int SEG, bool P1T>
 __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ sten, const T* __restrict__ u, int ldu,
                                                         const T* __restrict__ f, int ldf, T* __restrict__ fc,
                                                         int ldc, int nxc, int width, int nseg) {
@@ -245,9 +296,8 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
         const bool rv = k == 0 ? rv0 : (k == 4 ? rv4 : true);
         return (rv && inx(x)) ? v : T(0);
     };
-    // c(x) from u columns x-1, x, x+1 (U[k][0..2]) and f at rows fy-1..fy+1
-    auto colres = [&](int x, const T (*U)[3], const T* fv) -> T {
-        T r3[3];
+    // residuals r3[k] at (x, fy-1+k) from u columns x-1, x, x+1 (U[k][0..2]) and f at rows fy-1..fy+1
+    auto colres = [&](int x, const T (*U)[3], const T* fv, T* r3) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const T* st = stl + (k * NC + (x - xb)) * SP;
@@ -258,8 +308,11 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
                 for (int dx = 0; dx < 3; ++dx) acc -= st[dy * 3 + dx] * U[k + dy][dx];
             r3[k] = acc;
         }
-        return T(0.5) * r3[0] + r3[1] + T(0.5) * r3[2];
     };
+    auto mid = [](const T* r3) -> T { return T(0.5) * r3[0] + r3[1] + T(0.5) * r3[2]; };
+    // the column's share as the west / east neighbour column of a coarse node
+    auto west = [&](const T* r3) -> T { return P1T ? T(0.5) * (r3[0] + r3[1]) : T(0.5) * mid(r3); };
+    auto east = [&](const T* r3) -> T { return P1T ? T(0.5) * (r3[1] + r3[2]) : T(0.5) * mid(r3); };
     // ring slots: step i (X = X0 + i) loads u columns 2X+2, 2X+3 and f columns 2X+1, 2X+2
     T qu2[D][5], qu3[D][5], qf1[D][3], qf2[D][3];
     auto issue = [&](int i, int s) {
@@ -293,7 +346,12 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
         W[k][1] = zu(W[k][1], k, xb);
         W[k][2] = zu(W[k][2], k, xb + 1);
     }
-    T cprev = colres(xb, W, f0);
+    T cprev;  // west share of column 2X
+    {
+        T r3[3];
+        colres(xb, W, f0, r3);
+        cprev = west(r3);
+    }
 #pragma unroll
     for (int i = 0; i < SEG; ++i) {
         const int s = i % D;
@@ -318,10 +376,11 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
         }
         if (i + D < SEG) issue(i + D, s);
         if (X < X1) {
-            const T c1 = colres(x + 1, A, fa);
-            const T c2 = colres(x + 2, Bw, fb);
-            if (ok) fc[((size_t)Y * nxc + X) * ldc + t] = T(0.5) * cprev + c1 + T(0.5) * c2;
-            cprev = c2;
+            T r1[3], r2[3];
+            colres(x + 1, A, fa, r1);
+            colres(x + 2, Bw, fb, r2);
+            if (ok) fc[((size_t)Y * nxc + X) * ldc + t] = cprev + mid(r1) + east(r2);
+            cprev = west(r2);
         }
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
@@ -331,16 +390,18 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
     }
 }
 
-// Bilinear prolongation added to u for wide blocks (W >= 16 modes): a
-// workgroup walks kPrSeg nodes of one fine row; lanes are modes.  The fine
-// row takes the coarse row it lies on (odd y) or the mean of the two it lies
-// between (even y); along the row, odd x takes the coarse value it lies on
-// and even x the mean of its two neighbours.  Loads are clamped (zero
-// outside the coarse grid) and issued a ring of steps ahead.
+// Prolongation added to u for wide blocks (W >= 16 modes): a workgroup
+// walks kPrSeg nodes of one fine row; lanes are modes.  The fine row takes
+// the coarse row it lies on (odd y) or the mean of the two it lies between
+// (even y); along the row, odd x takes the coarse value it lies on and even
+// x the mean of its two neighbours.  With the P1 transfer (P1T) a node with
+// even x and even y (a fine cell centre) takes the mean of the coarse SW and
+// NE corners instead.  Loads are clamped (zero outside the coarse grid) and
+// issued a ring of steps ahead.
 constexpr int kPrSeg = 32;       // fine nodes per segment on the fine levels
 constexpr int kPrSegShort = 8;   // on coarse levels
 
-template <typename T, int SEG>
+template <typename T, int SEG, bool P1T>
 __global__ void __launch_bounds__(256) k_prolong_rows(const T* __restrict__ ec, int ldc, T* __restrict__ u, int ldu,
                                                       int nxf, int width, int nseg) {
     constexpr int D = 4;
@@ -365,11 +426,10 @@ __global__ void __launch_bounds__(256) k_prolong_rows(const T* __restrict__ ec, 
     auto cX = [&](int X) { return min(max(X, 0), nxc - 1); };
     auto gca = [&](int X) -> T { return ec[((size_t)yac * nxc + cX(X)) * ldc + tc]; };
     auto gcb = [&](int X) -> T { return ec[((size_t)ybc * nxc + cX(X)) * ldc + tc]; };
-    auto erow = [&](T a, T b, int X) -> T {
-        if (X < 0 || X >= nxc) return T(0);
-        const T av = va_ok ? a : T(0), bv = vb_ok ? b : T(0);
-        return (y & 1) ? av : wy * (av + bv);
-    };
+    // the coarse values below (a) and above (b) the fine row, zero outside
+    auto am = [&](T a, int X) -> T { return (X < 0 || X >= nxc || !va_ok) ? T(0) : a; };
+    auto bm = [&](T b, int X) -> T { return (X < 0 || X >= nxc || !vb_ok) ? T(0) : b; };
+    auto erow = [&](T av, T bv) -> T { return (y & 1) ? av : wy * (av + bv); };
     auto gu = [&](int x) -> T { return u[((size_t)y * nxf + min(x, nxf - 1)) * ldu + tc]; };
     const int Xs = x0 >> 1;  // step i covers fine columns 2(Xs+i), 2(Xs+i)+1
     T qa[D], qb[D], q0[D], q1[D];
@@ -383,45 +443,37 @@ __global__ void __launch_bounds__(256) k_prolong_rows(const T* __restrict__ ec, 
     T pa = gca(Xs - 1), pb = gcb(Xs - 1);
 #pragma unroll
     for (int s = 0; s < D; ++s) issue(s, s);
-    T eprev = erow(pa, pb, Xs - 1);
+    T aprev = am(pa, Xs - 1);
+    T eprev = erow(aprev, bm(pb, Xs - 1));
+    const bool centre = P1T && !(y & 1);  // even x on this row: SW / NE mean
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
         const int s = i % D;
         const int X = Xs + i;
-        const T e = erow(qa[s], qb[s], X);
+        const T a = am(qa[s], X), b = bm(qb[s], X);
+        const T e = erow(a, b);
         const T u0 = q0[s], u1 = q1[s];
         if (i + D < NIT) issue(i + D, s);
         const int xe = 2 * X, xo = 2 * X + 1;
-        if (ok && xe < x1) u[((size_t)y * nxf + xe) * ldu + t] = u0 + T(0.5) * (eprev + e);
+        const T ev = centre ? T(0.5) * (aprev + b) : T(0.5) * (eprev + e);
+        if (ok && xe < x1) u[((size_t)y * nxf + xe) * ldu + t] = u0 + ev;
         if (ok && xo < x1) u[((size_t)y * nxf + xo) * ldu + t] = u1 + e;
         eprev = e;
+        aprev = a;
     }
 }
 
 template <typename T, bool WAVE_NODE>
-__global__ void k_prolong_add(const T* __restrict__ ec, int ldc, T* __restrict__ u, int ldu, int nxf, int width) {
+__global__ void k_prolong_add(const T* __restrict__ ec, int ldc, T* __restrict__ u, int ldu, int nxf, int width,
+                              int p1) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
     int node = xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
     if (WAVE_NODE) node = __builtin_amdgcn_readfirstlane(node);  // one node per wavefront
     if (mode >= width || node >= nxf * nxf) return;
     const int y = node / nxf, x = node - y * nxf;
     const int nxc = (nxf - 1) / 2;
-    // fine x odd: on a coarse node (x-1)/2; x even: between coarse x/2-1 and x/2
-    int cx[2], cy[2], nxs, nys;
-    T wx, wy;
-    if (x & 1) { cx[0] = (x - 1) >> 1; nxs = 1; wx = T(1); }
-    else { cx[0] = (x >> 1) - 1; cx[1] = x >> 1; nxs = 2; wx = T(0.5); }
-    if (y & 1) { cy[0] = (y - 1) >> 1; nys = 1; wy = T(1); }
-    else { cy[0] = (y >> 1) - 1; cy[1] = y >> 1; nys = 2; wy = T(0.5); }
-    T acc = T(0);
-    for (int b = 0; b < nys; ++b) {
-        if (cy[b] < 0 || cy[b] >= nxc) continue;
-        for (int a = 0; a < nxs; ++a) {
-            if (cx[a] < 0 || cx[a] >= nxc) continue;
-            acc += ec[((size_t)cy[b] * nxc + cx[a]) * ldc + mode];
-        }
-    }
-    u[(size_t)node * ldu + mode] += wx * wy * acc;
+    auto get = [&](int X, int Y) { return ec[((size_t)Y * nxc + X) * ldc + mode]; };
+    u[(size_t)node * ldu + mode] += prolong_value<T>(get, nxc, x, y, p1 != 0);
 }
 
 // u = Kinv f for every column; one block per column, double arithmetic
@@ -652,6 +704,7 @@ struct FusedLevels {
     int off[kMaxFusedLevels];       // LDS element offset of u_l (f_l follows at off + N_l)
     const T* sten[kMaxFusedLevels];
     int roff;                       // LDS element offset of the residual / staging array
+    int p1;                         // transfer of the P1 triangulation (else bilinear)
 };
 
 template <typename T>
@@ -748,18 +801,7 @@ __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const d
         T* fc = lds + fl.off[l + 1] + Nc;
         for (int node = threadIdx.x; node < Nc; node += blockDim.x) {
             const int Y = node / nxc, X = node - Y * nxc;
-            const int fx = 2 * X + 1, fy = 2 * Y + 1;
-            T acc = T(0);
-#pragma unroll
-            for (int dy = -1; dy <= 1; ++dy) {
-                const T wy = dy == 0 ? T(1) : T(0.5);
-#pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const T wx = dx == 0 ? T(1) : T(0.5);
-                    acc += wx * wy * r[(fy + dy) * nx + (fx + dx)];
-                }
-            }
-            fc[node] = acc;
+            fc[node] = restrict_value<T>([&](int x, int y) { return r[y * nx + x]; }, X, Y, fl.p1 != 0);
         }
         __syncthreads();
     }
@@ -783,22 +825,7 @@ __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const d
         const T* ec = lds + fl.off[l + 1];
         for (int node = threadIdx.x; node < N; node += blockDim.x) {
             const int y = node / nx, x = node - y * nx;
-            int cx0, cx1, cy0, cy1;
-            T wx, wy;
-            if (x & 1) { cx0 = cx1 = (x - 1) >> 1; wx = T(1); } else { cx0 = (x >> 1) - 1; cx1 = x >> 1; wx = T(0.5); }
-            if (y & 1) { cy0 = cy1 = (y - 1) >> 1; wy = T(1); } else { cy0 = (y >> 1) - 1; cy1 = y >> 1; wy = T(0.5); }
-            T acc = T(0);
-            const int ncx = (cx0 == cx1) ? 1 : 2, ncy = (cy0 == cy1) ? 1 : 2;
-            for (int b = 0; b < ncy; ++b) {
-                const int cy = b ? cy1 : cy0;
-                if (cy < 0 || cy >= nxc) continue;
-                for (int a = 0; a < ncx; ++a) {
-                    const int cx = a ? cx1 : cx0;
-                    if (cx < 0 || cx >= nxc) continue;
-                    acc += ec[cy * nxc + cx];
-                }
-            }
-            u[node] += wx * wy * acc;
+            u[node] += prolong_value<T>([&](int X, int Y) { return ec[Y * nxc + X]; }, nxc, x, y, fl.p1 != 0);
         }
         __syncthreads();
         lds_smooth<T>(fl.sten[l], u, f, r, nx, rb, true, nu2);
@@ -898,7 +925,7 @@ __device__ __forceinline__ void coarsest_solve(const double* __restrict__ kinv, 
     __syncthreads();
 }
 
-// NT threads: at least the largest colour class of the top fused grid// NT threads: at least the largest colour class of the top fused grid
+// NT threads: at least the largest colour class of the top fused grid
 // (32 x 32 for 63 x 63 float grids, 16 x 16 for 31 x 31 double grids)
 template <typename T>
 constexpr int fused4_threads() { return sizeof(T) == 4 ? 1024 : 256; }
@@ -935,18 +962,7 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_fused4(FusedLeve
         T* fc = lds + fl.off[l + 1] + Nc;
         for (int node = threadIdx.x; node < Nc; node += blockDim.x) {
             const int Y = node / nxc, X = node - Y * nxc;
-            const int fx = 2 * X + 1, fy = 2 * Y + 1;
-            T acc = T(0);
-#pragma unroll
-            for (int dy = -1; dy <= 1; ++dy) {
-                const T wy = dy == 0 ? T(1) : T(0.5);
-#pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const T wx = dx == 0 ? T(1) : T(0.5);
-                    acc += wx * wy * r[(fy + dy) * nx + (fx + dx)];
-                }
-            }
-            fc[node] = acc;
+            fc[node] = restrict_value<T>([&](int x, int y) { return r[y * nx + x]; }, X, Y, fl.p1 != 0);
         }
         __syncthreads();
     }
@@ -960,23 +976,8 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_fused4(FusedLeve
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (on.node[q] < 0) continue;
-            const int x = on.x[q], y = on.y[q];
-            int cx0, cx1, cy0, cy1;
-            T wx, wy;
-            if (x & 1) { cx0 = cx1 = (x - 1) >> 1; wx = T(1); } else { cx0 = (x >> 1) - 1; cx1 = x >> 1; wx = T(0.5); }
-            if (y & 1) { cy0 = cy1 = (y - 1) >> 1; wy = T(1); } else { cy0 = (y >> 1) - 1; cy1 = y >> 1; wy = T(0.5); }
-            T acc = T(0);
-            const int ncx = (cx0 == cx1) ? 1 : 2, ncy = (cy0 == cy1) ? 1 : 2;
-            for (int b = 0; b < ncy; ++b) {
-                const int cy = b ? cy1 : cy0;
-                if (cy < 0 || cy >= nxc) continue;
-                for (int a = 0; a < ncx; ++a) {
-                    const int cx = a ? cx1 : cx0;
-                    if (cx < 0 || cx >= nxc) continue;
-                    acc += ec[cy * nxc + cx];
-                }
-            }
-            u[on.node[q]] += wx * wy * acc;
+            u[on.node[q]] += prolong_value<T>([&](int X, int Y) { return ec[Y * nxc + X]; }, nxc, on.x[q], on.y[q],
+                                              fl.p1 != 0);
         }
         __syncthreads();
         own_smooth<T>(on, u, f, nx, true, nu2);
@@ -1127,6 +1128,7 @@ template <typename T>
 int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     const Tile tl = tile_for(width);
     const int L = (int)c->levels.size() - 1;
+    const bool p1 = c->hs.disc == SG_DISC_P1;  // transfer of the P1 triangulation
     // first level handled by the fused LDS kernel (-1: none fits, coarsest solved by k_coarse)
     int Lc = -1;
     for (int l = 0; l <= L; ++l)
@@ -1153,8 +1155,9 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             const bool shortw = (long)lc.nx * ((lc.nx + kRrSeg - 1) / kRrSeg) * nws < kMinWalkWaves;
             const int seg = shortw ? kRrSegShort : kRrSeg;
             const int nseg = (lc.nx + seg - 1) / seg;
-            hipLaunchKernelGGL((shortw ? k_resid_restrict<T, kRrSegShort> : k_resid_restrict<T, kRrSeg>),
-                               dim3(lc.nx * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv), (const T*)u,
+            auto rr = shortw ? (p1 ? k_resid_restrict<T, kRrSegShort, true> : k_resid_restrict<T, kRrSegShort, false>)
+                             : (p1 ? k_resid_restrict<T, kRrSeg, true> : k_resid_restrict<T, kRrSeg, false>);
+            hipLaunchKernelGGL(rr, dim3(lc.nx * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv), (const T*)u,
                                uld(l), fptr(l), fld(l), LevelPtr<T>::f(lc), width, lc.nx, width, nseg);
         } else {
             T* r = LevelPtr<T>::r(lv);
@@ -1165,7 +1168,7 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
                 hipLaunchKernelGGL((k_residual<T, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
                                    LevelPtr<T>::s(lv), (const T*)u, uld(l), fptr(l), fld(l), r, width, lv.nx, width);
             hipLaunchKernelGGL(k_restrict<T>, grid2(lc.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                               (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width);
+                               (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width, (int)p1);
         }
     }
     if (Lc >= 0) {
@@ -1184,6 +1187,7 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             off += 2 * lv.N;
         }
         fl.roff = off;
+        fl.p1 = p1;
         off += c->levels[Lc].N;
         if (c->opt.colour_mode == SG_COLOUR_FOUR)
             hipLaunchKernelGGL(k_vcycle_fused4<T>, dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T),
@@ -1206,15 +1210,17 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             const bool shortw = (long)lv.nx * ((lv.nx + kPrSeg - 1) / kPrSeg) * nws < kMinWalkWaves;
             const int seg = shortw ? kPrSegShort : kPrSeg;
             const int nseg = (lv.nx + seg - 1) / seg;
-            hipLaunchKernelGGL((shortw ? k_prolong_rows<T, kPrSegShort> : k_prolong_rows<T, kPrSeg>), dim3(lv.nx * nseg),
+            auto pr = shortw ? (p1 ? k_prolong_rows<T, kPrSegShort, true> : k_prolong_rows<T, kPrSegShort, false>)
+                             : (p1 ? k_prolong_rows<T, kPrSeg, true> : k_prolong_rows<T, kPrSeg, false>);
+            hipLaunchKernelGGL(pr, dim3(lv.nx * nseg),
                                dim3(64 * nws), 0, c->stream, (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u,
                                uld(l), lv.nx, width, nseg);
         } else if (tl.tx == 64)
             hipLaunchKernelGGL((k_prolong_add<T, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width);
+                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width, (int)p1);
         else
             hipLaunchKernelGGL((k_prolong_add<T, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width);
+                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width, (int)p1);
         if (use_row_sweeps<T>(c, width))
             row_sweeps<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, c->opt.nu2, false);
         else

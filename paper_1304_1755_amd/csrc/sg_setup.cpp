@@ -133,19 +133,30 @@ bool cholesky_inverse(std::vector<double>& A, int n) {
     return true;
 }
 
-// Galerkin coarsening P^T K P of a 9-point operator on interior nodes, with
-// P the bilinear interpolation from the (nc-1)^2 coarse to the (2nc-1)^2 fine nodes.
-std::vector<double> rap(const std::vector<double>& Sf, int nf) {
+// Weight of coarse node J in the interpolated value at the fine node whose
+// offset from J's own fine position (2 J + 1 per axis) is (dx, dy), |dx|, |dy| <= 1.
+// Bilinear: (1 - |dx|/2)(1 - |dy|/2).  Linear interpolation on the triangles
+// of the south-west to north-east split (Sec. 6): the same on the grid lines;
+// a fine cell centre lies on the diagonal of its coarse cell, so it takes
+// 1/2 from the coarse SW and NE corners (dx = dy) and nothing from the others.
+double transfer_weight(int dx, int dy, bool p1) {
+    if (dx != 0 && dy != 0) return p1 ? (dx == dy ? 0.5 : 0.0) : 0.25;
+    return (dx == 0 ? 1.0 : 0.5) * (dy == 0 ? 1.0 : 0.5);
+}
+
+// Galerkin coarsening P^T K P of a 9-point operator on interior nodes, with P
+// the interpolation above from the (nc-1)^2 coarse to the (2nc-1)^2 fine nodes.
+std::vector<double> rap(const std::vector<double>& Sf, int nf, bool p1) {
     const int nc = nf / 2, nxf = nf - 1, nxc = nc - 1;
     std::vector<double> Sc((size_t)nxc * nxc * 9, 0.0);
-    auto wt = [](int d) { return d == 0 ? 1.0 : 0.5; };
     for (int Y = 0; Y < nxc; ++Y)
         for (int X = 0; X < nxc; ++X) {
             double* out = &Sc[((size_t)Y * nxc + X) * 9];
             for (int ay = -1; ay <= 1; ++ay)
                 for (int ax = -1; ax <= 1; ++ax) {
                     const int fx = 2 * X + 1 + ax, fy = 2 * Y + 1 + ay;  // fine node a
-                    const double pa = wt(ax) * wt(ay);
+                    const double pa = transfer_weight(ax, ay, p1);
+                    if (pa == 0.0) continue;
                     const double* st = &Sf[((size_t)fy * nxf + fx) * 9];
                     for (int ey = -1; ey <= 1; ++ey)
                         for (int ex = -1; ex <= 1; ++ex) {
@@ -153,25 +164,24 @@ std::vector<double> rap(const std::vector<double>& Sf, int nf) {
                             if (bx < 0 || by < 0 || bx >= nxf || by >= nxf) continue;
                             const double kab = st[(ey + 1) * 3 + (ex + 1)];
                             if (kab == 0.0) continue;
-                            // coarse nodes J with P(b, J) != 0
-                            int jx[2], jy[2], cx = 0, cy = 0;
-                            double wx[2], wy[2];
-                            if (bx % 2 == 1) { jx[0] = (bx - 1) / 2; wx[0] = 1.0; cx = 1; }
-                            else { jx[0] = bx / 2 - 1; jx[1] = bx / 2; wx[0] = wx[1] = 0.5; cx = 2; }
-                            if (by % 2 == 1) { jy[0] = (by - 1) / 2; wy[0] = 1.0; cy = 1; }
-                            else { jy[0] = by / 2 - 1; jy[1] = by / 2; wy[0] = wy[1] = 0.5; cy = 2; }
-                            for (int iy = 0; iy < cy; ++iy)
-                                for (int ix = 0; ix < cx; ++ix) {
-                                    const int JX = jx[ix], JY = jy[iy];
+                            // coarse neighbours J = (X + ox, Y + oy) with P(b, J) != 0
+                            for (int oy = -1; oy <= 1; ++oy)
+                                for (int ox = -1; ox <= 1; ++ox) {
+                                    const int JX = X + ox, JY = Y + oy;
                                     if (JX < 0 || JY < 0 || JX >= nxc || JY >= nxc) continue;
-                                    const int ox = JX - X, oy = JY - Y;
-                                    out[(oy + 1) * 3 + (ox + 1)] += pa * kab * wx[ix] * wy[iy];
+                                    const int dx = bx - (2 * JX + 1), dy = by - (2 * JY + 1);
+                                    if (dx < -1 || dx > 1 || dy < -1 || dy > 1) continue;
+                                    const double pb = transfer_weight(dx, dy, p1);
+                                    if (pb != 0.0) out[(oy + 1) * 3 + (ox + 1)] += pa * kab * pb;
                                 }
                         }
                 }
         }
     return Sc;
 }
+
+// f = 2 (1/2 - x^2 - y^2) on (-1/2, 1/2)^2 (Sec. 6)
+double paper_load(double x, double y) { return 2.0 * (0.5 - x * x - y * y); }
 
 }  // namespace
 
@@ -181,6 +191,12 @@ int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_a
     hs.m = m;
     hs.p = p;
     hs.N = (n - 1) * (n - 1);
+    hs.disc = opt.discretization;
+    const bool p1 = hs.disc == SG_DISC_P1;
+    // xi_k ~ U[-1, 1] (orthonormal Legendre chaos as is), or uniform with
+    // variance one (Sec. 6): xi = sqrt 3 eta with eta ~ U[-1, 1] scales the
+    // coupling E[xi q_a q_b] by sqrt 3
+    hs.gscale = p1 ? std::sqrt(3.0) : 1.0;
 
     // chaos index set and degree levels
     auto idx = graded_indices(m, p);
@@ -220,62 +236,157 @@ int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_a
         }
     }
 
-    // cell coefficients (midpoint rule per cell)
     const double h = 1.0 / n;
     const size_t ncell = (size_t)n * n;
-    hs.cellc.assign((size_t)(m + 1) * ncell, 0.0);
-    hs.klcell.assign((size_t)m * ncell, 0.0);
-    for (int cy = 0; cy < n; ++cy)
-        for (int cx = 0; cx < n; ++cx) {
-            const size_t e = (size_t)cy * n + cx;
-            double a0 = 1.0;
-            if (a0_nodal) {
-                const size_t v = (size_t)cy * (n + 1) + cx;
-                a0 = 0.25 * (a0_nodal[v] + a0_nodal[v + 1] + a0_nodal[v + n + 1] + a0_nodal[v + n + 2]);
-            }
-            hs.cellc[e] = a0;
-            const double t1 = (cx + 0.5) * h - 0.5, t2 = (cy + 0.5) * h - 0.5;
-            double spread = 0.0;
-            for (int k = 0; k < m; ++k) {
-                const double b = eval1d(m1[pick[k].first], t1) * eval1d(m1[pick[k].second], t2);
-                hs.klcell[(size_t)k * ncell + e] = b;
-                const double ck = opt.sigma * hs.amps[k] * b;
-                hs.cellc[(size_t)(k + 1) * ncell + e] = ck;
-                spread += std::fabs(ck);
-            }
-            const double margin = a0 - spread;
-            if (e == 0 || margin < hs.a_min_h) hs.a_min_h = margin;
-        }
-
-    // fine K_0 stencil from the cell means: node (x, y) touches cells
-    // SW (x, y), SE (x+1, y), NW (x, y+1), NE (x+1, y+1); element matrix
-    // entries 4/6 (own vertex), -1/6 (edge neighbour), -2/6 (opposite vertex).
     hs.mg_n.clear();
     hs.mg_sten.clear();
-    {
+    if (!p1) {
+        // cell coefficients (midpoint rule per cell)
+        hs.cellc.assign((size_t)(m + 1) * ncell, 0.0);
+        hs.klcell.assign((size_t)m * ncell, 0.0);
+        for (int cy = 0; cy < n; ++cy)
+            for (int cx = 0; cx < n; ++cx) {
+                const size_t e = (size_t)cy * n + cx;
+                double a0 = 1.0;
+                if (a0_nodal) {
+                    const size_t v = (size_t)cy * (n + 1) + cx;
+                    a0 = 0.25 * (a0_nodal[v] + a0_nodal[v + 1] + a0_nodal[v + n + 1] + a0_nodal[v + n + 2]);
+                }
+                hs.cellc[e] = a0;
+                const double t1 = (cx + 0.5) * h - 0.5, t2 = (cy + 0.5) * h - 0.5;
+                double spread = 0.0;
+                for (int k = 0; k < m; ++k) {
+                    const double b = eval1d(m1[pick[k].first], t1) * eval1d(m1[pick[k].second], t2);
+                    hs.klcell[(size_t)k * ncell + e] = b;
+                    const double ck = opt.sigma * hs.amps[k] * b;
+                    hs.cellc[(size_t)(k + 1) * ncell + e] = ck;
+                    spread += std::fabs(ck);
+                }
+                const double margin = a0 - spread;
+                if (e == 0 || margin < hs.a_min_h) hs.a_min_h = margin;
+            }
+
+        // fine K_0 stencil from the cell means: node (x, y) touches cells
+        // SW (x, y), SE (x+1, y), NW (x, y+1), NE (x+1, y+1); element matrix
+        // entries 4/6 (own vertex), -1/6 (edge neighbour), -2/6 (opposite vertex).
+        {
+            const int nx = n - 1;
+            std::vector<double> st((size_t)nx * nx * 9, 0.0);
+            for (int y = 0; y < nx; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const double sw = hs.cellc[(size_t)y * n + x], se = hs.cellc[(size_t)y * n + x + 1];
+                    const double nw = hs.cellc[(size_t)(y + 1) * n + x], ne = hs.cellc[(size_t)(y + 1) * n + x + 1];
+                    double* s = &st[((size_t)y * nx + x) * 9];
+                    s[0] = -2.0 * sw / 6.0;          // (-1,-1)
+                    s[1] = -(sw + se) / 6.0;         // ( 0,-1)
+                    s[2] = -2.0 * se / 6.0;          // (+1,-1)
+                    s[3] = -(sw + nw) / 6.0;         // (-1, 0)
+                    s[4] = 4.0 * (sw + se + nw + ne) / 6.0;
+                    s[5] = -(se + ne) / 6.0;         // (+1, 0)
+                    s[6] = -2.0 * nw / 6.0;          // (-1,+1)
+                    s[7] = -(nw + ne) / 6.0;         // ( 0,+1)
+                    s[8] = -2.0 * ne / 6.0;          // (+1,+1)
+                }
+            hs.mg_n.push_back(n);
+            hs.mg_sten.push_back(std::move(st));
+        }
+        hs.kcoef.assign(ncell * (m + 1), 0.0);
+        for (size_t e = 0; e < ncell; ++e)
+            for (int k = 0; k <= m; ++k) hs.kcoef[e * (m + 1) + k] = hs.cellc[(size_t)k * ncell + e] / 6.0;
+    } else {
+        // one value per triangle at its centroid: the lower triangle (SW, SE,
+        // NE) of cell (cx, cy) has its centroid at (cx + 2/3, cy + 1/3) h, the
+        // upper one (SW, NE, NW) at (cx + 1/3, cy + 2/3) h, measured from the
+        // corner (-1/2, -1/2); a0 = 1
+        const size_t ntri = 2 * ncell;
+        hs.cellc.assign((size_t)(m + 1) * ntri, 0.0);
+        hs.klcell.clear();
+        for (int up = 0; up < 2; ++up)
+            for (int cy = 0; cy < n; ++cy)
+                for (int cx = 0; cx < n; ++cx) {
+                    const size_t e = (size_t)up * ncell + (size_t)cy * n + cx;
+                    const double t1 = (cx + (up ? 1.0 : 2.0) / 3.0) * h - 0.5;
+                    const double t2 = (cy + (up ? 2.0 : 1.0) / 3.0) * h - 0.5;
+                    hs.cellc[e] = 1.0;
+                    double spread = 0.0;
+                    for (int k = 0; k < m; ++k) {
+                        const double b = eval1d(m1[pick[k].first], t1) * eval1d(m1[pick[k].second], t2);
+                        const double ck = opt.sigma * hs.amps[k] * b;
+                        hs.cellc[(size_t)(k + 1) * ntri + e] = ck;
+                        spread += std::fabs(ck);
+                    }
+                    const double margin = 1.0 - hs.gscale * spread;
+                    if (e == 0 || margin < hs.a_min_h) hs.a_min_h = margin;
+                }
+        // A right isosceles triangle couples the two ends of each leg with
+        // -1/2 of its coefficient and the ends of its hypotenuse with 0, so
+        // K_k is the 5-point operator sum_e w_{k,e} (u_i - u_j) over the grid
+        // edges e = (i, j), w_{k,e} the mean of the coefficients of the two
+        // triangles beside e (Dirichlet neighbours contribute u_j = 0).  The
+        // east edge of vertex (cx, cy) borders the lower triangle of cell
+        // (cx, cy) and the upper one of cell (cx, cy - 1); its north edge the
+        // upper triangle of cell (cx, cy) and the lower one of cell (cx - 1, cy).
+        auto tri = [&](int k, int up, int cx, int cy) -> double {
+            if (cx < 0 || cy < 0 || cx >= n || cy >= n) return 0.0;
+            return hs.cellc[(size_t)k * ntri + (size_t)up * ncell + (size_t)cy * n + cx];
+        };
+        const int W = 2 * (m + 1);
+        hs.kcoef.assign(ncell * W, 0.0);
+        for (int cy = 0; cy < n; ++cy)
+            for (int cx = 0; cx < n; ++cx)
+                for (int k = 0; k <= m; ++k) {
+                    double* w = &hs.kcoef[((size_t)cy * n + cx) * W];
+                    w[k] = 0.5 * (tri(k, 0, cx, cy) + tri(k, 1, cx, cy - 1));
+                    w[m + 1 + k] = 0.5 * (tri(k, 1, cx, cy) + tri(k, 0, cx - 1, cy));
+                }
+        // fine K_0 in the 9-point format: node (x, y) is vertex (x+1, y+1)
         const int nx = n - 1;
         std::vector<double> st((size_t)nx * nx * 9, 0.0);
+        auto ew = [&](int vx, int vy) { return hs.kcoef[((size_t)vy * n + vx) * W]; };
+        auto nw = [&](int vx, int vy) { return hs.kcoef[((size_t)vy * n + vx) * W + m + 1]; };
         for (int y = 0; y < nx; ++y)
             for (int x = 0; x < nx; ++x) {
-                const double sw = hs.cellc[(size_t)y * n + x], se = hs.cellc[(size_t)y * n + x + 1];
-                const double nw = hs.cellc[(size_t)(y + 1) * n + x], ne = hs.cellc[(size_t)(y + 1) * n + x + 1];
-                double* s = &st[((size_t)y * nx + x) * 9];
-                s[0] = -2.0 * sw / 6.0;          // (-1,-1)
-                s[1] = -(sw + se) / 6.0;         // ( 0,-1)
-                s[2] = -2.0 * se / 6.0;          // (+1,-1)
-                s[3] = -(sw + nw) / 6.0;         // (-1, 0)
-                s[4] = 4.0 * (sw + se + nw + ne) / 6.0;
-                s[5] = -(se + ne) / 6.0;         // (+1, 0)
-                s[6] = -2.0 * nw / 6.0;          // (-1,+1)
-                s[7] = -(nw + ne) / 6.0;         // ( 0,+1)
-                s[8] = -2.0 * ne / 6.0;          // (+1,+1)
+                const double wE = ew(x + 1, y + 1), wW = ew(x, y + 1), wN = nw(x + 1, y + 1), wS = nw(x + 1, y);
+                double* s9 = &st[((size_t)y * nx + x) * 9];
+                s9[1] = -wS;
+                s9[3] = -wW;
+                s9[4] = wE + wW + wN + wS;
+                s9[5] = -wE;
+                s9[7] = -wN;
             }
         hs.mg_n.push_back(n);
         hs.mg_sten.push_back(std::move(st));
+        // load vector: f phi_i is a cubic on every triangle; the rule with the
+        // centroid (weight -27/48) and the three points (3/5, 1/5, 1/5) in
+        // barycentric coordinates (weights 25/48) is exact for cubics
+        hs.load.assign(hs.N, 0.0);
+        const double area = 0.5 * h * h;
+        const double qb[4][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {0.6, 0.2, 0.2}, {0.2, 0.6, 0.2}, {0.2, 0.2, 0.6}};
+        const double qw[4] = {-27.0 / 48, 25.0 / 48, 25.0 / 48, 25.0 / 48};
+        for (int up = 0; up < 2; ++up)
+            for (int cy = 0; cy < n; ++cy)
+                for (int cx = 0; cx < n; ++cx) {
+                    // corners (grid vertex coordinates): lower SW, SE, NE; upper SW, NE, NW
+                    const int vx[3] = {cx, cx + 1, up ? cx : cx + 1};
+                    const int vy[3] = {cy, up ? cy + 1 : cy, cy + 1};
+                    double loc[3] = {0.0, 0.0, 0.0};
+                    for (int q = 0; q < 4; ++q) {
+                        double px = 0.0, py = 0.0;
+                        for (int i = 0; i < 3; ++i) {
+                            px += qb[q][i] * (vx[i] * h - 0.5);
+                            py += qb[q][i] * (vy[i] * h - 0.5);
+                        }
+                        const double fq = qw[q] * area * paper_load(px, py);
+                        for (int i = 0; i < 3; ++i) loc[i] += fq * qb[q][i];
+                    }
+                    for (int i = 0; i < 3; ++i)
+                        if (vx[i] > 0 && vy[i] > 0 && vx[i] < n && vy[i] < n)
+                            hs.load[(size_t)(vy[i] - 1) * nx + (vx[i] - 1)] += loc[i];
+                }
     }
     while (hs.mg_n.back() > opt.coarsest_cells) {
         const int nf = hs.mg_n.back();
-        hs.mg_sten.push_back(rap(hs.mg_sten.back(), nf));
+        hs.mg_sten.push_back(rap(hs.mg_sten.back(), nf, p1));
         hs.mg_n.push_back(nf / 2);
     }
     {
@@ -334,7 +445,7 @@ PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_o
                 auto it = pos.find(b);
                 if (it == pos.end() || it->second < in_lo || it->second >= in_lo + W_in) continue;
                 // E[xi q_a q_{a+1}] = b_{a+1}: up partner uses a = alpha_k, down partner a = alpha_k - 1
-                const double g = dir == 0 ? legendre_b(al[k] + 1) : legendre_b(al[k]);
+                const double g = hs.gscale * (dir == 0 ? legendre_b(al[k] + 1) : legendre_b(al[k]));
                 const uint32_t idx = (uint32_t)(k * lanes + (it->second - in_lo));
                 uint32_t& w = pl.off[(size_t)t * (L / 2) + k];
                 if (dir == 0) w = (w & 0xFFFF0000u) | idx;

@@ -78,3 +78,28 @@ def test_not_coercive_is_a_warning():
     import paper_1304_1755_amd as sgbt
     hs = sgbt.setup_host(16, 4, 2, 3.0, 0.5)
     assert hs["code"] == sgbt.SG_WNOTCOERCIVE and hs["a_min_h"] < 0
+
+
+@pytest.mark.parametrize("n,m,p,sigma", [(16, 3, 2, 0.3), (32, 6, 1, 0.1)])
+def test_p1_setup_matches_the_papers_discretisation(n, m, p, sigma):
+    # SG_DISC_P1 against the oracle's Sec. 6 problem: triangle coefficients, the 5-point fine
+    # K_0, its Galerkin coarsening with the P1 transfer, and the coarsest inverse
+    import paper_1304_1755_amd as sgbt
+    from oracle import paper_mode
+    hs = sgbt.setup_host(n, m, p, sigma, 1.0, coarsest=4, disc="p1")
+    pr = paper_mode.build_problem_paper(n, m, p, sigma)
+    assert hs["cell"].shape == pr.cellc.shape
+    assert np.max(np.abs(hs["cell"] - pr.cellc)) < 1e-13
+    amin = np.min(pr.cellc[0] - np.sqrt(3.0) * np.abs(pr.cellc[1:]).sum(axis=0))
+    assert abs(hs["a_min_h"] - amin) < 1e-13
+    H = mg.Hierarchy(pr.K[0], n, coarsest=4, transfer="p1")
+    ref0 = _matrix_rows(H.K[0], n)
+    ok = ~np.isnan(ref0)
+    assert np.max(np.abs(hs["fine"][ok] - ref0[ok])) < 1e-14
+    ref1 = _matrix_rows(H.K[1], n // 2)
+    ok1 = ~np.isnan(ref1)
+    assert np.max(np.abs(hs["l1"][ok1] - ref1[ok1])) < 1e-13
+    # the P1 coarse operator keeps the triangulation's 7-point pattern: no NW / SE entries
+    assert np.max(np.abs(hs["l1"][:, [2, 6]])) < 1e-14
+    Kc = H.K[-1].toarray()
+    assert np.max(np.abs(hs["cinv"] - np.linalg.inv(Kc))) < 1e-11 * np.max(np.abs(hs["cinv"]))
