@@ -80,6 +80,38 @@ def cpu_baseline(seconds=10.0):
             "host_cpu_count": os.cpu_count(), "blas_threads": blas}
 
 
+def paper_table3(sgbt, stream):
+    """Iterations and time to 1e-10 of the five solvers of Table 3 on the paper's own problem
+    (P1 triangles, h = 1/64, m = 6, p = 4, L = 1, 833,490 unknowns) for sigma = 0.1 .. 0.4,
+    beside the printed counts (the paper's smoother is lexicographic, ours four-colour)."""
+    golden = {}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_numbers.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if "=" in line:
+                k, v = line.split("=", 1)
+                golden[k.strip()] = v.strip()
+    solvers = [("block GS", dict(solver="bgs", precond="tri")), ("BD-PCG", dict(solver="pcg", precond="diag")),
+               ("BT-GPCG", dict(solver="gpcg", precond="tri")),
+               ("BT-GMRes(10)", dict(solver="fgmres", precond="tri", restart=10)),
+               ("BS-PCG", dict(solver="pcg", precond="sym"))]
+    rows = {}
+    for sigma in (0.1, 0.2, 0.3, 0.4):
+        pr = sgbt.Problem(64, 6, 4, sigma, corr_len=1.0, coarsest=4, disc="p1", stream=stream)
+        F = pr.rhs()
+        X = pr.empty()
+        its, ms = [], []
+        for _, kw in solvers:
+            pr.solve(F, X, rtol=1e-10, max_it=300, **kw)  # warm
+            _, info = pr.solve(F, X, rtol=1e-10, max_it=300, **kw)
+            its.append(info["iters"] if info["status"] == 0 else None)
+            ms.append(info["t_total_ms"])
+        pr.close()
+        rows[str(sigma)] = {"iters": its, "ms": ms,
+                            "paper_iters": [int(v) for v in golden[f"table3_iters_sigma_{sigma}"].split()]}
+    return {"solvers": [name for name, _ in solvers], "rtol": 1e-10, "unknowns": 833490, "sigma": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +122,7 @@ def main():
     ap.add_argument("--mode", default="full", choices=["full", "apply"],
                     help="apply: only the double apply loop (for profiler counter runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-paper", action="store_true", help="skip the Sec. 6 iteration-count table")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -210,6 +243,9 @@ def main():
                      "launches_timed": len(apply_ms)},
     }
     prob.close()
+    if not args.no_paper:
+        progress("the paper's Sec. 6 problem (P1, h = 1/64, m = 6, p = 4): Table 3 solvers")
+        out["paper_sec6_table3"] = paper_table3(sgbt, stream)
     if not args.no_cpu:
         progress("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline()
