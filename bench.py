@@ -33,6 +33,13 @@ METRIC = "SG apply GB/s + time to 1e-8 residual, mixed vs FP64 GMRES, at P=210"
 HBM_PEAK_GBS = 8000.0
 
 
+def apply_flops(N, P, m):
+    """FP64 flops per double apply as the kernel computes it (FMA = 2): per node and mode the
+    four cell residuals r_e (1 + 4 x 4), the m+1 stencil sums (4 FMAs each) and the 2m
+    coupling gathers (one FMA each)."""
+    return N * P * (17 + 8 * (m + 1) + 4 * m)
+
+
 def apply_bytes(N, P, n, m, in_bytes=8, out_bytes=8):
     """Algorithmic bytes of one apply: read U, write Y, read the (m+1) cell coefficient fields once."""
     return N * P * (in_bytes + out_bytes) + 8 * n * n * (m + 1)
@@ -119,8 +126,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3")
     ap.add_argument("--burst", type=int, default=12, help="double applies timed per step")
-    ap.add_argument("--mode", default="full", choices=["full", "apply"],
-                    help="apply: only the double apply loop (for profiler counter runs)")
+    ap.add_argument("--mode", default="full", choices=["full", "apply", "paper"],
+                    help="apply: only the double apply loop (for profiler counter runs); "
+                         "paper: only the Sec. 6 Table 3 solvers")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-paper", action="store_true", help="skip the Sec. 6 iteration-count table")
     args = ap.parse_args()
@@ -138,6 +146,9 @@ def main():
     torch.cuda.set_device(0)
     c = sg_inputs.CONFIGS[args.config]
     stream = torch.cuda.current_stream()
+    if args.mode == "paper":
+        print(json.dumps({"mode": "paper", "paper_sec6_table3": paper_table3(sgbt, stream)}))
+        return
     prob = sgbt.Problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"], colour="four", nu1=2, nu2=2,
                         coarsest=8, stream=stream)
     N, P, n, m = prob.N, prob.P, c["n"], c["m"]
@@ -240,7 +251,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sg_apply (double in/out)", "algorithmic_bytes_per_launch": nbytes,
                      "avg_launch_ms": avg_apply_ms, "median_launch_ms": med_apply_ms,
-                     "launches_timed": len(apply_ms)},
+                     "launches_timed": len(apply_ms),
+                     "fp64_tflops": apply_flops(N, P, m) / (avg_apply_ms * 1e-3) / 1e12,
+                     "fp64_vector_peak_tflops": 78.6},
     }
     prob.close()
     if not args.no_paper:
