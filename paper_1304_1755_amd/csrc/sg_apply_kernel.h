@@ -52,7 +52,8 @@ __device__ __forceinline__ int remap_block_xcd(int b, int nb) {
     return x * q + (x < r ? x : r) + i;
 }
 
-constexpr int kApplyRows = 2;  // grid rows per workgroup
+constexpr int kApplyRows = 2;        // grid rows per workgroup
+constexpr int kMinApplyWaves = 2048;  // below this many wavefronts a launch takes shorter segments
 
 template <typename F, int... J>
 __device__ __forceinline__ void unroll_steps(F&& f, std::integer_sequence<int, J...>) {
@@ -250,7 +251,10 @@ hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, cons
                     int ldy, const double* cell, int n, const void* zin) {
     constexpr int RW = kApplyRows;
     const int nx = n - 1;
-    const int seg = 32;
+    // 32-node segments; on small grids shorter ones, down to 8, so that the launch still has
+    // enough wavefronts to cover the chip (each segment's walk is sequential)
+    int seg = 32;
+    while (seg > 8 && (long)((nx + RW - 1) / RW) * ((nx + seg - 1) / seg) * NS < kMinApplyWaves) seg >>= 1;
     const int nseg = (nx + seg - 1) / seg;
     const int blocks = (nx + RW - 1) / RW * nseg;
     if (R)
