@@ -37,3 +37,30 @@ def test_invalid_options_are_rejected_without_a_device():
         sgbt.setup_host(32, 9, 2, 0.3)      # m > 8
     with pytest.raises(sgbt.SGError):
         sgbt.setup_host(32, 2, 2, 0.3, coarsest=12)   # 32 is not 12 * 2^L
+
+
+def test_discretisation_option_is_checked_without_a_device():
+    import ctypes
+
+    import numpy as np
+
+    import paper_1304_1755_amd as sgbt
+    lib = sgbt.load_library()
+    opt = sgbt.Options(n_cells=16, m=2, p=2, sigma=0.1, corr_len=1.0, colour_mode=0, nu1=2, nu2=2,
+                       coarsest_cells=4, discretization=7)
+    assert lib.sg_setup_host(ctypes.byref(opt), None, None, None, None, None, None, None, None) == sgbt.SG_EINVAL
+    # the Sec. 6 setting takes a0 = 1: a nodal mean field is refused
+    a0 = np.ones(17 * 17)
+    opt.discretization = sgbt.SG_DISC_P1
+    P = ctypes.POINTER(ctypes.c_double)
+    assert lib.sg_setup_host(ctypes.byref(opt), a0.ctypes.data_as(P), None, None, None, None, None, None,
+                             None) == sgbt.SG_EINVAL
+    assert lib.sg_setup_host(ctypes.byref(opt), None, None, None, None, None, None, None, None) == sgbt.SG_OK
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
