@@ -124,22 +124,42 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     const uint32_t tco = vout ? t : W_out - 1;
     Tin wb[NR][C];
     double qr[RW][D];  // R at (x, y0 + q) lives in qr[q][(x - x0) mod D]
+    // row bases, computed once: the window rows y0-1 .. y0+RW (and which lie in
+    // the grid), the R and Y rows of the segment's nodes
+    const Tin* rowb[NR];
+    bool rowin[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int yy = y0 + r - 1;
+        rowin[r] = yy >= 0 && yy < nx;
+        rowb[r] = U + (size_t)(rowin[r] ? yy : 0) * nx * ldu;
+    }
+    const double* rrow[RW];
+    Tout* yrow[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        const int yq = min(y0 + q, nx - 1);
+        rrow[q] = HAS_R ? R + (size_t)yq * nx * ldr : R;
+        yrow[q] = Y + (size_t)yq * nx * ldy;
+    }
+    // coefficient rows y0 .. y0+RW (cells, or vertices for TRI): (M+1) or 2(M+1) values per position
+    const double* crow[RW + 1];
+#pragma unroll
+    for (int r = 0; r <= RW; ++r) crow[r] = cell + (size_t)min(y0 + r, n - 1) * n * (TRI ? 2 * (M + 1) : M + 1);
     auto load_col = [&](int c, int xc) {
+        const bool colin = xc >= 0 && xc < nx;  // uniform
+        const size_t xo = (size_t)(colin ? xc : 0) * ldu;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int yy = y0 + r - 1;
-            const bool inside = yy >= 0 && yy < nx && xc >= 0 && xc < nx;  // uniform
-            const Tin* rowp = inside ? U + ((size_t)yy * nx + xc) * ldu : zin;
+            const Tin* rowp = (rowin[r] && colin) ? rowb[r] + xo : zin;
             wb[r][c] = rowp[tci];
         }
     };
     auto load_r = [&](int c, int x) {
         if (HAS_R) {
+            const size_t xo = (size_t)min(x, nx - 1) * ldr;
 #pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                const int yq = min(y0 + q, nx - 1);
-                qr[q][c % D] = R[((size_t)yq * nx + min(x, nx - 1)) * ldr + tco];
-            }
+            for (int q = 0; q < RW; ++q) qr[q][c % D] = rrow[q][xo + tco];
         }
     };
     // columns x0-1 .. x0+D and R at x0 .. x0+D-1
@@ -173,9 +193,9 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
                 // its east edges for k = 0..M, then its north edges.  West edge = east
                 // edge of vertex (x, y0+q+1); south edge = north edge of vertex (x+1, y0+q).
                 constexpr int CW = 2 * (M + 1);
-                const double* pC = cell + ((size_t)(y0 + q + 1) * n + x + 1) * CW;
+                const double* pC = crow[q + 1] + (x + 1) * CW;
                 const double* pW = pC - CW;
-                const double* pS = cell + ((size_t)(y0 + q) * n + x + 1) * CW + (M + 1);
+                const double* pS = crow[q] + (x + 1) * CW + (M + 1);
                 const double* pN = pC + (M + 1);
                 const double dE = wc - wE, dW = wc - wW, dN = wc - wN, dS = wc - wS;
                 s0[q] = fma(pC[0], dE, fma(pW[0], dW, fma(pN[0], dN, pS[0] * dS)));
@@ -187,9 +207,9 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
             // node (x, y0 + q); cells SW (x, y0+q), SE (x+1, y0+q), NW (x, y0+q+1), NE (x+1, y0+q+1)
             const double wSW = (double)wb[q][cW], wSE = (double)wb[q][cE];
             const double wNW = (double)wb[q + 2][cW], wNE = (double)wb[q + 2][cE];
-            const double* cSW = cell + ((size_t)(y0 + q) * n + x) * (M + 1);
+            const double* cSW = crow[q] + x * (M + 1);
             const double* cSE = cSW + (M + 1);
-            const double* cNW = cell + ((size_t)(y0 + q + 1) * n + x) * (M + 1);
+            const double* cNW = crow[q + 1] + x * (M + 1);
             const double* cNE = cNW + (M + 1);
             const double uc4 = 4.0 * wc;
             const double rSW = fma(-2.0, wSW, uc4 - (wS + wW));
@@ -221,10 +241,7 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
                     acc = fma(ce[2 * jj], Bq[off[jj] & 0xFFFFu], acc);
                     acc = fma(ce[2 * jj + 1], Bq[off[jj] >> 16], acc);
                 }
-                if (vout) {
-                    const size_t node = (size_t)(y0 + q) * nx + x;
-                    st_from_double(Y + node * ldy + t, HAS_R ? rv[q] - acc : acc);
-                }
+                if (vout) st_from_double(yrow[q] + (size_t)x * ldy + t, HAS_R ? rv[q] - acc : acc);
             }
         }
         if (NBUF == 1) {
