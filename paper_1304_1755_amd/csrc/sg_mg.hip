@@ -287,11 +287,16 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
     const bool rv0 = fy - 2 >= 0, rv4 = fy + 2 < nxf;
     auto cx = [&](int x) { return min(max(x, 0), nxf - 1); };
     auto inx = [&](int x) { return x >= 0 && x < nxf; };
-    auto gu = [&](int k, int x) -> T {
-        const int yy = min(max(fy - 2 + k, 0), nxf - 1);
-        return u[((size_t)yy * nxf + cx(x)) * ldu + tc];
-    };
-    auto gf = [&](int k, int x) -> T { return f[((size_t)(fy - 1 + k) * nxf + x) * ldf + tc]; };
+    // row bases computed once (fine rows fy-2 .. fy+2 of u clamped into the grid, rows fy-1 .. fy+1 of f)
+    const T* urow[5];
+    const T* frow[3];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) urow[k] = u + (size_t)min(max(fy - 2 + k, 0), nxf - 1) * nxf * ldu;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) frow[k] = f + (size_t)(fy - 1 + k) * nxf * ldf;
+    T* const fcrow = fc + (size_t)Y * nxc * ldc;
+    auto gu = [&](int k, int x) -> T { return (urow[k] + cx(x) * ldu)[tc]; };
+    auto gf = [&](int k, int x) -> T { return (frow[k] + x * ldf)[tc]; };
     auto zu = [&](T v, int k, int x) -> T {
         const bool rv = k == 0 ? rv0 : (k == 4 ? rv4 : true);
         return (rv && inx(x)) ? v : T(0);
@@ -379,7 +384,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
             T r1[3], r2[3];
             colres(x + 1, A, fa, r1);
             colres(x + 2, Bw, fb, r2);
-            if (ok) fc[((size_t)Y * nxc + X) * ldc + t] = cprev + mid(r1) + east(r2);
+            if (ok) (fcrow + X * ldc)[t] = cprev + mid(r1) + east(r2);
             cprev = west(r2);
         }
 #pragma unroll
@@ -424,13 +429,16 @@ __global__ void __launch_bounds__(256) k_prolong_rows(const T* __restrict__ ec, 
     const bool va_ok = ya >= 0, vb_ok = (y & 1) ? false : yb < nxc;
     const int yac = max(ya, 0), ybc = min(yb, nxc - 1);
     auto cX = [&](int X) { return min(max(X, 0), nxc - 1); };
-    auto gca = [&](int X) -> T { return ec[((size_t)yac * nxc + cX(X)) * ldc + tc]; };
-    auto gcb = [&](int X) -> T { return ec[((size_t)ybc * nxc + cX(X)) * ldc + tc]; };
+    const T* const earow = ec + (size_t)yac * nxc * ldc;
+    const T* const ebrow = ec + (size_t)ybc * nxc * ldc;
+    T* const urow = u + (size_t)y * nxf * ldu;
+    auto gca = [&](int X) -> T { return (earow + cX(X) * ldc)[tc]; };
+    auto gcb = [&](int X) -> T { return (ebrow + cX(X) * ldc)[tc]; };
     // the coarse values below (a) and above (b) the fine row, zero outside
     auto am = [&](T a, int X) -> T { return (X < 0 || X >= nxc || !va_ok) ? T(0) : a; };
     auto bm = [&](T b, int X) -> T { return (X < 0 || X >= nxc || !vb_ok) ? T(0) : b; };
     auto erow = [&](T av, T bv) -> T { return (y & 1) ? av : wy * (av + bv); };
-    auto gu = [&](int x) -> T { return u[((size_t)y * nxf + min(x, nxf - 1)) * ldu + tc]; };
+    auto gu = [&](int x) -> T { return (urow + min(x, nxf - 1) * ldu)[tc]; };
     const int Xs = x0 >> 1;  // step i covers fine columns 2(Xs+i), 2(Xs+i)+1
     T qa[D], qb[D], q0[D], q1[D];
     auto issue = [&](int i, int s) {
@@ -456,8 +464,8 @@ __global__ void __launch_bounds__(256) k_prolong_rows(const T* __restrict__ ec, 
         if (i + D < NIT) issue(i + D, s);
         const int xe = 2 * X, xo = 2 * X + 1;
         const T ev = centre ? T(0.5) * (aprev + b) : T(0.5) * (eprev + e);
-        if (ok && xe < x1) u[((size_t)y * nxf + xe) * ldu + t] = u0 + ev;
-        if (ok && xo < x1) u[((size_t)y * nxf + xo) * ldu + t] = u1 + e;
+        if (ok && xe < x1) (urow + xe * ldu)[t] = u0 + ev;
+        if (ok && xo < x1) (urow + xo * ldu)[t] = u1 + e;
         eprev = e;
         aprev = a;
     }
@@ -549,9 +557,16 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     __syncthreads();
     auto cx = [&](int x) { return min(max(x, 0), nx - 1); };
     auto inx = [&](int x) { return x >= 0 && x < nx; };
-    auto gA = [&](int x) -> T { return OWNZ ? T(0) : A[((size_t)y * nx + cx(x)) * lda + tc]; };
-    auto gV = [&](int yy, int x) -> T { return V[((size_t)yy * nx + cx(x)) * ldv + tc]; };
-    auto gf = [&](int x) -> T { return f[((size_t)y * nx + cx(x)) * ldf + tc]; };
+    // row bases computed once: own row of A, f and B, the rows below and above in V
+    const T* const arow = A + (size_t)y * nx * lda;
+    const T* const frow = f + (size_t)y * nx * ldf;
+    const T* const dnrow = V + (size_t)ydn * nx * ldv;
+    const T* const uprow = V + (size_t)yup * nx * ldv;
+    T* const brow = B + (size_t)y * nx * ldb;
+    auto gA = [&](int x) -> T { return OWNZ ? T(0) : (arow + cx(x) * lda)[tc]; };
+    auto gD = [&](int x) -> T { return (dnrow + cx(x) * ldv)[tc]; };
+    auto gU = [&](int x) -> T { return (uprow + cx(x) * ldv)[tc]; };
+    auto gf = [&](int x) -> T { return (frow + cx(x) * ldf)[tc]; };
     auto zA = [&](T v, int x) -> T { return (!OWNZ && inx(x)) ? v : T(0); };
     auto zD = [&](T v, int x) -> T { return (has_dn && inx(x)) ? v : T(0); };
     auto zU = [&](T v, int x) -> T { return (has_up && inx(x)) ? v : T(0); };
@@ -573,14 +588,14 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
         qa[k] = gA(s + 2);
         qfs[k] = gf(s);
         qff[k] = gf(s + 1);
-        qd1[k] = gV(ydn, s + 1);
-        qd2[k] = gV(ydn, s + 2);
-        qu1[k] = gV(yup, s + 1);
-        qu2[k] = gV(yup, s + 2);
+        qd1[k] = gD(s + 1);
+        qd2[k] = gD(s + 2);
+        qu1[k] = gU(s + 1);
+        qu2[k] = gU(s + 2);
     };
     // prologue: window columns sf-2 .. sf, own values at sf-2 and sf, f(sf-1)
-    T dm = gV(ydn, sf - 2), d0 = gV(ydn, sf - 1), d1 = gV(ydn, sf);
-    T um = gV(yup, sf - 2), u0 = gV(yup, sf - 1), u1 = gV(yup, sf);
+    T dm = gD(sf - 2), d0 = gD(sf - 1), d1 = gD(sf);
+    T um = gU(sf - 2), u0 = gU(sf - 1), u1 = gU(sf);
     T am = gA(sf - 2), Sold = gA(sf);
     const T fp = gf(sf - 1);
 #pragma unroll
@@ -592,7 +607,7 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     T Fprev = T(0);
     if (sf - 1 >= 0) {
         Fprev = relax(sf - 1, fp, am, Sold, dm, d0, d1, um, u0, u1);
-        if (!fx && ok) B[((size_t)y * nx + sf - 1) * ldb + t] = Fprev;
+        if (!fx && ok) (brow + (sf - 1) * ldb)[t] = Fprev;
     }
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
@@ -607,12 +622,12 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
         T Fnew = T(0);
         if (s + 1 < nx) {
             Fnew = relax(s + 1, fF, Sold, Snext, d1, d2, d3, u1, u2, u3);
-            if (s + 1 < x1 && ok) B[((size_t)y * nx + s + 1) * ldb + t] = Fnew;
+            if (s + 1 < x1 && ok) (brow + (s + 1) * ldb)[t] = Fnew;
         }
         // S(s) from new F(s-1), F(s+1)
         if (s < x1) {
             const T Snew = relax(s, fS, Fprev, Fnew, d0, d1, d2, u0, u1, u2);
-            if (ok) B[((size_t)y * nx + s) * ldb + t] = Snew;
+            if (ok) (brow + s * ldb)[t] = Snew;
         }
         d0 = d2;
         d1 = d3;
