@@ -63,6 +63,9 @@ extern "C" {
 /* smoother colourings for the multigrid V-cycle */
 #define SG_COLOUR_FOUR 0 /* colour (I mod 2) + 2 (J mod 2): exact Gauss-Seidel for the 9-point stencil */
 #define SG_COLOUR_RB 1   /* colour (I + J) mod 2, each colour updated from its start-of-colour values */
+#define SG_COLOUR_LEX 2  /* lexicographic point Gauss-Seidel (x fastest), forward before and backward after
+                            the coarse correction: the smoother of Sec. 6.  Sequential fronts: for grids of
+                            the paper's sizes, not for throughput */
 
 /* discretisations (see above) */
 #define SG_DISC_Q1 0
@@ -76,11 +79,11 @@ typedef struct {
     int p;              /* total chaos degree, 0..8, with P = (m+p)!/(m!p!) <= 256 */
     double sigma;       /* standard deviation scale of the field (Sec. 2.1, eq. (exponential-covariance)) */
     double corr_len;    /* correlation length L > 0 */
-    int colour_mode;    /* SG_COLOUR_FOUR or SG_COLOUR_RB */
+    int colour_mode;    /* SG_COLOUR_FOUR, SG_COLOUR_RB or SG_COLOUR_LEX */
     int nu1, nu2;       /* pre- and post-smoothing sweeps of the V-cycle, 0..8 */
     int coarsest_cells; /* cells per side of the coarsest grid (>= 2); equal to n_cells gives exact K_0 solves */
     int discretization; /* SG_DISC_Q1 (0) or SG_DISC_P1 (1); SG_DISC_P1 takes a0 = 1 (a0_nodal NULL),
-                           SG_COLOUR_FOUR, and has no sg_qoi / sg_qoi_grad */
+                           SG_COLOUR_FOUR or SG_COLOUR_LEX, and has no sg_qoi / sg_qoi_grad */
 } sg_options;
 
 typedef struct {

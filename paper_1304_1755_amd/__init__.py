@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsgbt.so")
 SG_OK, SG_WNOTCOERCIVE = 0, 1
 SG_EINVAL, SG_ENOMEM, SG_EHIP, SG_ENOTCONV, SG_ENAN = -1, -2, -3, -4, -5
 SG_F64, SG_F32, SG_MIXED = 0, 1, 2
-SG_COLOUR_FOUR, SG_COLOUR_RB = 0, 1
+SG_COLOUR_FOUR, SG_COLOUR_RB, SG_COLOUR_LEX = 0, 1, 2
 SG_DISC_Q1, SG_DISC_P1 = 0, 1
 DISCRETIZATIONS = {"q1": SG_DISC_Q1, "p1": SG_DISC_P1}
 
@@ -163,7 +163,7 @@ class Problem:
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt = Options(n_cells=n, m=m, p=p, sigma=sigma, corr_len=corr_len,
-                      colour_mode={"four": SG_COLOUR_FOUR, "rb": SG_COLOUR_RB}[colour], nu1=nu1, nu2=nu2,
+                      colour_mode={"four": SG_COLOUR_FOUR, "rb": SG_COLOUR_RB, "lex": SG_COLOUR_LEX}[colour], nu1=nu1, nu2=nu2,
                       coarsest_cells=coarsest, discretization=DISCRETIZATIONS[disc])
         a0p = amp = None
         a0_keep = amp_keep = None

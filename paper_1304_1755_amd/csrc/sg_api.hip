@@ -621,13 +621,14 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
     if (n < 4 || n > 4096 || n % 4 != 0 || opt->m < 0 || opt->m > kMaxM || opt->p < 0 || opt->p > 8 || nc < 2 ||
         nc > n || n % nc != 0 || ((n / nc) & (n / nc - 1)) != 0 || (nc - 1) * (nc - 1) > 4096 ||
         !(opt->corr_len > 0.0) || opt->nu1 < 0 || opt->nu1 > 8 || opt->nu2 < 0 || opt->nu2 > 8 ||
-        (opt->colour_mode != SG_COLOUR_FOUR && opt->colour_mode != SG_COLOUR_RB) || !std::isfinite(opt->sigma) ||
+        (opt->colour_mode != SG_COLOUR_FOUR && opt->colour_mode != SG_COLOUR_RB && opt->colour_mode != SG_COLOUR_LEX) ||
+        !std::isfinite(opt->sigma) ||
         (opt->discretization != SG_DISC_Q1 && opt->discretization != SG_DISC_P1)) {
         set_error("sg_setup: invalid options (need n % 4 == 0, n = coarsest * 2^L, m <= 8, p <= 8, ...)");
         return SG_EINVAL;
     }
-    if (opt->discretization == SG_DISC_P1 && (a0_nodal || opt->colour_mode != SG_COLOUR_FOUR)) {
-        set_error("sg_setup: SG_DISC_P1 takes a0 = 1 (a0_nodal NULL) and SG_COLOUR_FOUR");
+    if (opt->discretization == SG_DISC_P1 && (a0_nodal || opt->colour_mode == SG_COLOUR_RB)) {
+        set_error("sg_setup: SG_DISC_P1 takes a0 = 1 (a0_nodal NULL) and SG_COLOUR_FOUR or SG_COLOUR_LEX");
         return SG_EINVAL;
     }
     {

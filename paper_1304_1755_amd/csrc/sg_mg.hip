@@ -10,7 +10,9 @@
 // block is a contiguous run of W values.
 //
 // Components: multi-colour Gauss-Seidel (four colours (I mod 2, J mod 2), or
-// red/black with each colour updated from its start-of-colour values),
+// red/black with each colour updated from its start-of-colour values) or
+// the lexicographic point Gauss-Seidel of Sec. 6 (front by front, one
+// workgroup per right-hand side; for grids of the paper's sizes),
 // residual, restriction R = P^T, prolongation P, and the coarsest grid
 // solved with the explicit inverse of its operator in double precision.  P is
 // the bilinear interpolation for Q1 elements, or the linear interpolation of
@@ -725,9 +727,55 @@ struct FusedLevels {
 template <typename T>
 constexpr int fused_nx_max() { return sizeof(T) == 4 ? 63 : 31; }
 
+// one relaxation of node (x, y) against the current values of its neighbours
+template <typename T, typename G>
+__device__ __forceinline__ T relax_node(const T* __restrict__ s9, T fval, int x, int y, int nx, G get) {
+    T acc = fval;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= nx) continue;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            const int xx = x + dx;
+            if (xx < 0 || xx >= nx) continue;
+            acc -= s9[(dy + 1) * 3 + (dx + 1)] * get(yy * nx + xx);
+        }
+    }
+    return acc / s9[4];
+}
+
+// Lexicographic order (x fastest, then y) for a 9-point stencil: the
+// neighbours of (x, y) that come earlier all have a smaller x + 2y and the
+// later ones a larger, so the nodes of one front x + 2y = d are independent
+// and a sweep visits the 3(nx-1)+1 fronts in order (backward: in reverse).
+// Front d holds y = ylo..yhi with x = d - 2y.
+__device__ __forceinline__ void lex_front(int d, int nx, int& ylo, int& yhi) {
+    ylo = max(0, (d - nx + 2) / 2);
+    yhi = min(nx - 1, d / 2);
+}
+
+// mode 0: four colours; 1: red/black from start-of-colour values; 2: lexicographic
 template <typename T>
-__device__ void lds_smooth(const T* __restrict__ st, T* u, const T* f, T* stage, int nx, bool rb, bool reverse,
+__device__ void lds_smooth(const T* __restrict__ st, T* u, const T* f, T* stage, int nx, int mode, bool reverse,
                            int nu) {
+    if (mode == 2) {
+        const int nd = 3 * (nx - 1) + 1;
+        for (int sweep = 0; sweep < nu; ++sweep)
+            for (int di = 0; di < nd; ++di) {
+                const int d = reverse ? nd - 1 - di : di;
+                int ylo, yhi;
+                lex_front(d, nx, ylo, yhi);
+                for (int y = ylo + (int)threadIdx.x; y <= yhi; y += blockDim.x) {
+                    const int x = d - 2 * y, node = y * nx + x;
+                    u[node] = relax_node<T>(st + (size_t)node * 9, f[node], x, y, nx, [&](int i) { return u[i]; });
+                }
+                __syncthreads();
+            }
+        return;
+    }
+    const bool rb = mode == 1;
     const int ncol = rb ? 2 : 4;
     for (int sweep = 0; sweep < nu; ++sweep)
         for (int qi = 0; qi < ncol; ++qi) {
@@ -770,10 +818,36 @@ __device__ void lds_smooth(const T* __restrict__ st, T* u, const T* f, T* stage,
         }
 }
 
+// One lexicographic Gauss-Seidel sweep (forward, or backward when reverse)
+// on the separate-launch levels: one workgroup per right-hand-side column
+// walks the fronts of lex_front in place, with a workgroup barrier between
+// fronts.  zero_start: the column starts from zero (cleared here).
+template <typename T>
+__global__ void __launch_bounds__(256) k_gs_lex(const T* __restrict__ sten, T* u, int ldu, const T* __restrict__ f,
+                                                int ldf, int nx, int reverse, int zero_start) {
+    const int col = blockIdx.x;
+    if (zero_start) {
+        for (int i = threadIdx.x; i < nx * nx; i += blockDim.x) u[(size_t)i * ldu + col] = T(0);
+        __syncthreads();
+    }
+    const int nd = 3 * (nx - 1) + 1;
+    for (int di = 0; di < nd; ++di) {
+        const int d = reverse ? nd - 1 - di : di;
+        int ylo, yhi;
+        lex_front(d, nx, ylo, yhi);
+        for (int y = ylo + (int)threadIdx.x; y <= yhi; y += blockDim.x) {
+            const int x = d - 2 * y, node = y * nx + x;
+            u[(size_t)node * ldu + col] = relax_node<T>(sten + (size_t)node * 9, f[(size_t)node * ldf + col], x, y,
+                                                       nx, [&](int i) { return u[(size_t)i * ldu + col]; });
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const double* __restrict__ kinv,
                                                       const T* __restrict__ fin, int ldf, T* __restrict__ uout,
-                                                      int ldu, int nu1, int nu2, int rb) {
+                                                      int ldu, int nu1, int nu2, int mode) {
     extern __shared__ char smem_raw[];
     T* lds = (T*)smem_raw;
     T* r = lds + fl.roff;
@@ -791,7 +865,7 @@ __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const d
         T* f = u + N;
         for (int i = threadIdx.x; i < N; i += blockDim.x) u[i] = T(0);
         __syncthreads();
-        lds_smooth<T>(fl.sten[l], u, f, r, nx, rb, false, nu1);
+        lds_smooth<T>(fl.sten[l], u, f, r, nx, mode, false, nu1);
         // residual r = f - K u
         for (int node = threadIdx.x; node < N; node += blockDim.x) {
             const int y = node / nx, x = node - y * nx;
@@ -843,7 +917,7 @@ __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const d
             u[node] += prolong_value<T>([&](int X, int Y) { return ec[Y * nxc + X]; }, nxc, x, y, fl.p1 != 0);
         }
         __syncthreads();
-        lds_smooth<T>(fl.sten[l], u, f, r, nx, rb, true, nu2);
+        lds_smooth<T>(fl.sten[l], u, f, r, nx, mode, true, nu2);
     }
     {
         const int N0 = fl.nx[0] * fl.nx[0];
@@ -1043,6 +1117,11 @@ void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, boo
             bool first) {
     Level& lv = c->levels[l];
     const int nx = lv.nx;
+    if (c->opt.colour_mode == SG_COLOUR_LEX) {
+        hipLaunchKernelGGL(k_gs_lex<T>, dim3(width), dim3(256), 0, c->stream, LevelPtr<T>::s(lv), u, ldu, f, ldf, nx,
+                           reverse ? 1 : 0, first ? 1 : 0);
+        return;
+    }
     const bool rb = c->opt.colour_mode == SG_COLOUR_RB;
     const int ncol = rb ? 2 : 4;
     for (int qi = 0; qi < ncol; ++qi) {
@@ -1211,7 +1290,7 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
         else
             hipLaunchKernelGGL(k_vcycle_fused<T>, dim3(width), dim3(512), (size_t)off * sizeof(T), c->stream, fl,
                                (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2,
-                               1);
+                               c->opt.colour_mode == SG_COLOUR_LEX ? 2 : 1);
     } else {
         Level& lc = c->levels[L];
         hipLaunchKernelGGL(k_coarse<T>, dim3(width), dim3(256), (size_t)lc.N * sizeof(double), c->stream, c->kinv,

@@ -51,6 +51,25 @@ def test_apply_and_residual_match_oracle(n, m, p, sigma):
     g.close()
 
 
+def test_apply_full_size_separable():
+    # the Sec. 6 discretisation at the bench's grid (513 x 513 vertices, m = 6, p = 4, P = 210,
+    # 54.8M unknowns, the launch configuration of the timed apply): for a separable input
+    # U = sum_r v_r w_r^T the exact result is sum_r sum_k (K_k v_r)(G_k w_r)^T, formed from the
+    # oracle's K_k and G_k
+    note("p1 apply full size separable")
+    import paper_1304_1755_amd as sgbt
+    g = sgbt.Problem(512, 6, 4, 0.2, corr_len=1.0, coarsest=4, disc="p1")
+    o = paper_mode.build_problem_paper(512, 6, 4, 0.2)
+    V, W = sg_inputs.separable_factors(g.N, g.P, rank=2)
+    Y = to_host(g.apply(to_dev(V.T @ W)))
+    ref = np.zeros((g.N, g.P))
+    for r in range(2):
+        for Gk, Kk in zip(o.G, o.K):
+            ref += np.outer(Kk @ V[r], Gk @ W[r])
+    assert rel_max(Y, ref) < 1e-12
+    g.close()
+
+
 def test_load_vector_matches_oracle():
     note("p1 rhs")
     g, o = _pair(32, 3, 2, 0.1)
@@ -186,6 +205,72 @@ def test_table2_counts_are_robust_in_h_and_p():
     ref = _oracle_counts(o, ["bd-pcg", "bt-gpcg", "bt-gmres", "bs-pcg"])
     for it, r in zip(counts[(32, 3)], ref):
         assert abs(it - r) <= 1, (counts[(32, 3)], ref)
+
+
+@pytest.mark.parametrize("disc,n,width,prec", [("p1", 64, 35, 0), ("p1", 64, 6, 1), ("q1", 64, 21, 0),
+                                                 ("q1", 128, 35, 1)])
+def test_lexicographic_vcycle_matches_oracle(disc, n, width, prec):
+    # the smoother of Sec. 6: lexicographic point Gauss-Seidel, forward before and backward
+    # after the coarse correction; separate-launch levels and the fused coarse cycle
+    note(f"lex vcycle {disc} n={n} width={width} prec={prec}")
+    import torch
+    import paper_1304_1755_amd as sgbt
+    if disc == "p1":
+        g = sgbt.Problem(n, 4, 3, 0.3, corr_len=1.0, coarsest=4, disc="p1", colour="lex")
+        o = paper_mode.build_problem_paper(n, 4, 3, 0.3)
+        H = mg.Hierarchy(o.K[0], n, coarsest=4, colour_mode="lex", transfer="p1")
+    else:
+        g = sgbt.Problem(n, 4, 3, 0.3, coarsest=8, colour="lex")
+        o = system.build_problem(n, 4, 3, 0.3)
+        H = mg.Hierarchy(o.K[0], n, coarsest=8, colour_mode="lex")
+    f = sg_inputs.uniform_block(g.N, width, seed=23)
+    ref = H.vcycle(f)
+    dt = torch.float64 if prec == 0 else torch.float32
+    u = to_host(g.vcycle(to_dev(f, dtype=dt), prec=prec))
+    assert rel_max(u, ref) < (1e-11 if prec == 0 else 2e-5)
+    g.close()
+
+
+def _lex_counts(pr, names):
+    A = system.assemble_A(pr)
+    H = mg.Hierarchy(pr.K[0], pr.n, coarsest=4, colour_mode="lex", transfer="p1")
+    F = pr.rhs().ravel()
+    Av = lambda v: A @ v  # noqa: E731
+
+    def M(fn):
+        return lambda v: fn(pr, v.reshape(pr.P, pr.N), H.vcycle).ravel()
+
+    run = {
+        "bgs": lambda: krylov.block_gs(Av, F, M(precond.precond_tri), tol=1e-10, max_it=300),
+        "bd-pcg": lambda: krylov.pcg(Av, F, M(precond.precond_diag), tol=1e-10),
+        "bt-gpcg": lambda: krylov.gpcg1(Av, F, M(precond.precond_tri), tol=1e-10),
+        "bt-gmres": lambda: krylov.fgmres(Av, F, M(precond.precond_tri), restart=10, tol=1e-10),
+        "bs-pcg": lambda: krylov.pcg(Av, F, M(precond.precond_sym), tol=1e-10),
+    }
+    return [run[k]()[1]["iters"] for k in names]
+
+
+def test_table3_with_the_papers_smoother():
+    # Table 3 at sigma = 0.1 with the lexicographic V(2,2) of Sec. 6: the five solvers' counts
+    # equal the oracle's (same smoother) within one and the printed ones within one
+    note("p1 table 3 lexicographic")
+    import paper_1304_1755_amd as sgbt
+    paper = [int(v) for v in golden()["table3_iters_sigma_0.1"].split()]
+    g = sgbt.Problem(64, 6, 4, 0.1, corr_len=1.0, coarsest=4, disc="p1", colour="lex")
+    runs = [dict(solver="bgs", precond="tri"), dict(solver="pcg", precond="diag"),
+            dict(solver="gpcg", precond="tri"), dict(solver="fgmres", precond="tri", restart=10),
+            dict(solver="pcg", precond="sym")]
+    got = []
+    for kw in runs:
+        _, info = g.solve(rtol=1e-10, max_it=300, **kw)
+        assert info["status"] == 0 and info["rel_res_true"] < 1e-10, (kw, info["status"])
+        got.append(info["iters"])
+    g.close()
+    ref = _lex_counts(paper_mode.build_problem_paper(64, 6, 4, 0.1), ["bgs", "bd-pcg", "bt-gpcg", "bt-gmres", "bs-pcg"])
+    note(f"p1 table 3 lexicographic: gpu {got}, oracle {ref}, paper {paper}")
+    for it, r, pp in zip(got, ref, paper):
+        assert abs(it - r) <= 1, (got, ref)
+        assert abs(it - pp) <= 1, (got, paper)
 
 
 def test_mixed_precision_solve_reaches_tolerance():
