@@ -273,6 +273,34 @@ def test_table3_with_the_papers_smoother():
         assert abs(it - pp) <= 1, (got, paper)
 
 
+def test_table2_with_the_papers_smoother():
+    # Table 2 (sigma = 0.1, m = 4, h = 1/32 .. 1/128, p = 2 .. 4) with the lexicographic V(2,2):
+    # every count within one of the printed one (BD-PCG 13, BT-GPCG 9, BT-GMRes 8, BS-PCG 9),
+    # whatever h and p
+    note("p1 table 2 lexicographic")
+    import paper_1304_1755_amd as sgbt
+    g0 = golden()
+    paper = [int(g0["table2_iters_BD_PCG"]), int(g0["table2_iters_BT_GPCG"]), int(g0["table2_iters_BT_GMRes"]),
+             int(g0["table2_iters_BT_GPCG"])]
+    runs = [dict(solver="pcg", precond="diag"), dict(solver="gpcg", precond="tri"),
+            dict(solver="fgmres", precond="tri", restart=10), dict(solver="pcg", precond="sym")]
+    counts = {}
+    for n in (32, 64, 128):
+        for p in (2, 3, 4):
+            g = sgbt.Problem(n, 4, p, 0.1, corr_len=1.0, coarsest=4, disc="p1", colour="lex")
+            its = []
+            for kw in runs:
+                _, info = g.solve(rtol=1e-10, max_it=300, **kw)
+                assert info["status"] == 0 and info["rel_res_true"] < 1e-10, (n, p, kw)
+                its.append(info["iters"])
+            g.close()
+            counts[(n, p)] = its
+    note(f"p1 table 2 lexicographic counts {counts} (paper {paper})")
+    for its in counts.values():
+        for it, pp in zip(its, paper):
+            assert abs(it - pp) <= 1, (counts, paper)
+
+
 def test_mixed_precision_solve_reaches_tolerance():
     note("p1 mixed solve")
     g, o = _pair(64, 4, 3, 0.3)
