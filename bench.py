@@ -11,10 +11,18 @@ One step = one pass of the whole hot path on that system:
   * one block-triangular-preconditioned FGMRES(30) solve to a 1e-8 true
     relative residual with float V(2,2) cycles and double Krylov / residuals
     (the mixed-precision solve; its wall time is the time to 1e-8).
-After the timed steps the all-double solve of the same problem is timed the
-same way, for the mixed-vs-double comparison.  The oracle (CPU, double) is
-timed on a bounded sample: its SG apply on the 65 x 65 copy of the workload
-(same m, p, sigma; 833,490 unknowns).
+The solve's clock starts after the stream has drained (the applies queued
+before it are not part of its time).  After the timed steps the all-double
+solve of the same problem is timed the same way, for the mixed-vs-double
+comparison, one more solve of each precision is run with per-phase HIP
+event timing (apply / preconditioner / orthogonalisation), and the two
+solutions are compared.  The 1025 x 1025 workload (m = 8, p = 3, P = 165,
+GMRES(20)) is measured the same way in a block of its own.  The oracle (CPU,
+double) is timed on bounded samples of the 65 x 65 copy of the workload (same
+m, p, sigma; 833,490 unknowns): its SG apply, and its block-triangular
+FGMRES(30) solve to 1e-8; its direct solution of that system is the
+reference that the GPU's mixed-precision solve of the same copy is compared
+against.
 
 Prints ONE JSON line.
 """
@@ -59,13 +67,16 @@ def traffic_from_profile(kernel_src, config):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(seconds=10.0):
-    """Oracle SG apply (scipy CSR, double) on the 65 x 65 copy of the workload."""
+def cpu_baseline(sgbt, stream, seconds=10.0):
+    """The oracle (scipy, double) on the 65 x 65 copy of the workload: its SG apply (CSR, one
+    thread) for about `seconds`, its block-triangular FGMRES(30) V(2,2) solve to 1e-8, and its
+    direct solution, against which the GPU's mixed-precision solve of the same copy is compared."""
     import numpy as np
+    import torch
     from threadpoolctl import threadpool_info
 
     import sg_inputs
-    from oracle import system
+    from oracle import krylov, mg, precond, system
     c = sg_inputs.CONFIGS["c3_65"]
     o = system.build_problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"])
     A = system.assemble_A(o)
@@ -79,11 +90,35 @@ def cpu_baseline(seconds=10.0):
     dt = (time.perf_counter() - t0) / k
     del y
     nbytes = apply_bytes(o.N, o.P, o.n, o.m)
+    # time to 1e-8 of the oracle's FGMRES with the level-sweep B_T and V(2,2) blocks
+    H = mg.Hierarchy(o.K[0], o.n, coarsest=8)
+    F = o.rhs().ravel()
+
+    def bt(r):
+        return precond.precond_tri(o, r.reshape(o.P, o.N), H.vcycle).ravel()
+
+    t0 = time.perf_counter()
+    _xo, oinfo = krylov.fgmres(lambda v: A @ v, F, bt, restart=30, tol=1e-8)
+    t_fgmres = time.perf_counter() - t0
+    Ustar = system.solve_direct(o, A=A)               # (P, N) reference solution
+    # the GPU's mixed-precision solve of the same copy, against the reference
+    g = sgbt.Problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"], coarsest=8, stream=stream)
+    Xg, ginfo = g.solve(precond="tri", prec=sgbt.SG_MIXED, restart=30, rtol=1e-8, max_it=300)
+    Xh = Xg.cpu().numpy().T                           # (P, N)
+    g.close()
+    err = float(np.linalg.norm(Xh - Ustar) / np.linalg.norm(Ustar))
+    res = float(np.linalg.norm(F - A @ Xh.ravel()) / np.linalg.norm(F))
     blas = sum(i.get("num_threads", 0) for i in threadpool_info()) or None
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} oracle applies (scipy CSR A @ x, {A.nnz} nnz) on the 65x65 copy of the workload "
                       f"(n=64, m=6, p=4, P=210, 833490 unknowns), {dt * 1e3:.1f} ms each; algorithmic bytes "
-                      f"{nbytes / 1e6:.1f} MB per apply as for the GPU line",
+                      f"{nbytes / 1e6:.1f} MB per apply as for the GPU line; then one oracle B_T-FGMRES(30) "
+                      f"V(2,2) solve of the same copy to 1e-8",
+            "time_to_1e-8_s": t_fgmres, "iters": oinfo["iters"],
+            "error_vs_oracle_65": {"what": "GPU mixed-precision B_T-FGMRES(30) solve of the 65x65 copy to 1e-8 "
+                                           "against the oracle's direct solution: ||U_gpu - U*|| / ||U*||",
+                                   "rel_error": err, "gpu_true_rel_res_oracle_matrix": res,
+                                   "gpu_iters": ginfo["iters"]},
             "host_cpu_count": os.cpu_count(), "blas_threads": blas}
 
 
@@ -136,6 +171,7 @@ def main():
                          "paper: only the Sec. 6 Table 3 solvers")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-paper", action="store_true", help="skip the Sec. 6 iteration-count table")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 1025x1025 workload block")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -190,6 +226,9 @@ def main():
             s.record(stream)
             prob.apply(U, Y)
             e.record(stream)
+        # the applies finish before the solve starts; sg_solve also drains the
+        # stream before it starts its own clock
+        stream.synchronize()
         _, info = prob.solve(F, X, precond="tri", prec=sgbt.SG_MIXED, restart=c["restart"], rtol=1e-8,
                              max_it=300)
         if timed:
@@ -216,6 +255,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall / args.steps * 1e3
+    X_mixed = X.clone()
 
     # all-double solve of the same problem, same algorithm (outside the timed steps)
     d_solves = []
@@ -224,6 +264,18 @@ def main():
         d_solves.append(info)
         progress(f"double solve: {info['iters']} it {info['t_total_ms']:.1f} ms")
     torch.cuda.synchronize()
+    diff = float(torch.linalg.vector_norm(X_mixed - X) / torch.linalg.vector_norm(X))
+    # where the solve time goes: one more solve of each precision with per-phase HIP events
+    split = {}
+    for name, prec in (("mixed", sgbt.SG_MIXED), ("fp64", sgbt.SG_F64)):
+        _, info = prob.solve(F, X, precond="tri", prec=prec, restart=c["restart"], rtol=1e-8, max_it=300,
+                             timing=True)
+        split[name] = {"total_ms": info["t_total_ms"], "apply_ms": info["t_apply_ms"],
+                       "precond_ms": info["t_prec_ms"], "orth_ms": info["t_orth_ms"],
+                       "other_ms": info["t_total_ms"] - info["t_apply_ms"] - info["t_prec_ms"] - info["t_orth_ms"],
+                       "applies": info["n_apply"], "preconds": info["n_prec"], "iters": info["iters"]}
+        progress(f"phase split {name}: {split[name]}")
+    del U, Y
 
     avg_apply_ms = float(np.mean(apply_ms))
     med_apply_ms = float(np.median(apply_ms))
@@ -251,7 +303,9 @@ def main():
         "time_to_1e-8_s": {"mixed": t_mixed, "fp64": t_f64, "speedup_mixed_vs_fp64": t_f64 / t_mixed,
                            "iters_mixed": solves[-1]["iters"], "iters_fp64": d_solves[-1]["iters"],
                            "true_rel_res_mixed": solves[-1]["rel_res_true"],
-                           "true_rel_res_fp64": d_solves[-1]["rel_res_true"]},
+                           "true_rel_res_fp64": d_solves[-1]["rel_res_true"],
+                           "rel_diff_mixed_vs_fp64": diff,
+                           "phase_split": split},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sg_apply (double in/out)", "algorithmic_bytes_per_launch": nbytes,
@@ -261,13 +315,73 @@ def main():
                      "fp64_vector_peak_tflops": 78.6},
     }
     prob.close()
+    del F, X, X_mixed
+    torch.cuda.empty_cache()
+    if not args.no_c4:
+        progress("the 1025x1025 workload (m = 8, p = 3, P = 165)")
+        out["c4"] = second_workload(sgbt, stream, "c4", args.burst, max(2, min(args.steps, 5)), progress)
     if not args.no_paper:
         progress("the paper's Sec. 6 problem (P1, h = 1/64, m = 6, p = 4): Table 3 solvers")
         out["paper_sec6_table3"] = paper_table3(sgbt, stream)
     if not args.no_cpu:
         progress("oracle CPU baseline")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(sgbt, stream)
     print(json.dumps(out))
+
+
+def second_workload(sgbt, stream, name, burst, solves, progress):
+    """Apply GB/s and mixed / double time to 1e-8 on another workload preset (inputs resident in HBM)."""
+    import numpy as np
+    import torch
+
+    import sg_inputs
+    c = sg_inputs.CONFIGS[name]
+    prob = sgbt.Problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"], colour="four", nu1=2, nu2=2,
+                        coarsest=8, stream=stream)
+    N, P = prob.N, prob.P
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1234)
+    U = torch.rand((N, P), dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+    Y = torch.empty_like(U)
+    nbytes = apply_bytes(N, P, c["n"], c["m"])
+    for _ in range(2):
+        prob.apply(U, Y)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(burst)]
+    for s, e in ev:
+        s.record(stream)
+        prob.apply(U, Y)
+        e.record(stream)
+    torch.cuda.synchronize()
+    ms = [s.elapsed_time(e) for s, e in ev]
+    del U, Y
+    F = prob.rhs()
+    X = torch.empty((N, P), dtype=torch.float64, device="cuda")
+    res = {}
+    for tag, prec in (("mixed", sgbt.SG_MIXED), ("fp64", sgbt.SG_F64)):
+        infos = []
+        for _ in range(solves + 1):  # the first is a warm-up
+            _, info = prob.solve(F, X, precond="tri", prec=prec, restart=c["restart"], rtol=1e-8, max_it=300)
+            infos.append(info)
+        progress(f"{name} {tag} solve: {infos[-1]['iters']} it {infos[-1]['t_total_ms']:.1f} ms")
+        res[tag] = infos[1:]
+        if tag == "mixed":
+            X_mixed = X.clone()
+    diff = float(torch.linalg.vector_norm(X_mixed - X) / torch.linalg.vector_norm(X))
+    prob.close()
+    del F, X, X_mixed
+    torch.cuda.empty_cache()
+    avg = float(np.mean(ms))
+    t_m = float(np.median([i["t_total_ms"] for i in res["mixed"]])) / 1e3
+    t_d = float(np.median([i["t_total_ms"] for i in res["fp64"]])) / 1e3
+    return {"workload": f"{name}: Q1 {c['n'] + 1}x{c['n'] + 1} grid (N={N}), m={c['m']}, p={c['p']}, P={P} "
+                        f"({N * P} unknowns), sigma={c['sigma']}, L={c['corr_len']}; B_T-FGMRES({c['restart']}) V(2,2)",
+            "apply": {"achieved_GBs": nbytes / (avg * 1e-3) / 1e9, "frac_of_peak": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "avg_launch_ms": avg, "algorithmic_bytes_per_launch": nbytes, "launches_timed": len(ms)},
+            "time_to_1e-8_s": {"mixed": t_m, "fp64": t_d, "speedup_mixed_vs_fp64": t_d / t_m,
+                               "iters_mixed": res["mixed"][-1]["iters"], "iters_fp64": res["fp64"][-1]["iters"],
+                               "true_rel_res_mixed": res["mixed"][-1]["rel_res_true"],
+                               "true_rel_res_fp64": res["fp64"][-1]["rel_res_true"],
+                               "rel_diff_mixed_vs_fp64": diff}}
 
 
 if __name__ == "__main__":

@@ -54,6 +54,9 @@ extern "C" {
 #define SG_EHIP (-3)      /* a HIP runtime call failed; see sg_last_error() */
 #define SG_ENOTCONV (-4)  /* solver stopped at max_it above the tolerance (result still written) */
 #define SG_ENAN (-5)      /* a residual norm became NaN or Inf */
+#define SG_EBREAKDOWN (-6) /* the Krylov recurrence broke down without a usable step (a zero or
+                              negative curvature (A p, p) in the CG-type solvers, or no Arnoldi column
+                              in the first FGMRES step); U holds the last iterate */
 
 /* precisions */
 #define SG_F64 0   /* all arithmetic and storage in double */
@@ -176,7 +179,9 @@ int sg_precond_sym(sg_ctx* ctx, const void* R, void* Z, int prec);
 
 /* Solve A U = F (Sec. 4.2 with Sec. 6 stopping rule).  F, U: device doubles
  * (U holds x0 if opts->use_x0).  info: host, may be NULL.  Returns SG_OK,
- * SG_ENOTCONV or SG_ENAN (U holds the last iterate) or an error. */
+ * SG_ENOTCONV, SG_ENAN or SG_EBREAKDOWN (U holds the last iterate) or an
+ * error.  Work queued earlier on the context's stream is finished before the
+ * solve's clock (info->t_total_ms) starts. */
 int sg_solve(sg_ctx* ctx, const double* F, double* U, const sg_solve_opts* opts, sg_solve_info* info);
 
 /* SG_DISC_Q1 only (SG_EINVAL otherwise).

@@ -18,14 +18,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsgbt.so")
 
 SG_OK, SG_WNOTCOERCIVE = 0, 1
-SG_EINVAL, SG_ENOMEM, SG_EHIP, SG_ENOTCONV, SG_ENAN = -1, -2, -3, -4, -5
+SG_EINVAL, SG_ENOMEM, SG_EHIP, SG_ENOTCONV, SG_ENAN, SG_EBREAKDOWN = -1, -2, -3, -4, -5, -6
 SG_F64, SG_F32, SG_MIXED = 0, 1, 2
 SG_COLOUR_FOUR, SG_COLOUR_RB, SG_COLOUR_LEX = 0, 1, 2
 SG_DISC_Q1, SG_DISC_P1 = 0, 1
 DISCRETIZATIONS = {"q1": SG_DISC_Q1, "p1": SG_DISC_P1}
 
 EXPORTED = ["sg_setup", "sg_query", "sg_get_cell_coeffs", "sg_rhs", "sg_apply", "sg_residual", "sg_vcycle",
-            "sg_precond_diag", "sg_precond_tri", "sg_precond_sym", "sg_solve", "sg_qoi", "sg_qoi_grad", "sg_setup_host", "sg_sync",
+            "sg_precond_diag", "sg_precond_tri", "sg_precond_sym", "sg_solve", "sg_qoi", "sg_qoi_grad",
+            "sg_setup_host", "sg_sync",
             "sg_destroy", "sg_last_error"]
 
 
@@ -298,28 +299,36 @@ class SGQoI(torch.autograd.Function):
     forward builds the system for the given parameters and solves it;
     backward returns the adjoint gradient computed by the library
     (sg_qoi_grad).  Inputs are CPU float64 tensors: sigma (scalar), s (m
-    amplitudes) and a0 ((n+1)^2 nodal mean field, boundary values included;
-    only interior values receive a gradient).
+    amplitudes) and a0_interior ((n-1)^2 values of the nodal mean field at the
+    interior vertices, x fastest).  The boundary vertices of a0 are data, not
+    parameters: cfg["a0_boundary"] (an (n+1)^2 array whose interior entries
+    are ignored) or 1 when absent.  Every input that enters J receives its
+    exact gradient.
     """
 
     @staticmethod
-    def forward(ctx, sigma, amps, a0, cfg):
-        prob = Problem(cfg["n"], cfg["m"], cfg["p"], float(sigma), corr_len=cfg.get("corr_len", 0.5),
-                       a0_nodal=a0.detach().cpu().numpy(), kl_amp=amps.detach().cpu().numpy(),
+    def forward(ctx, sigma, amps, a0_interior, cfg):
+        import numpy as np
+        n = cfg["n"]
+        if a0_interior.numel() != (n - 1) ** 2:
+            raise ValueError(f"a0_interior must hold (n-1)^2 = {(n - 1) ** 2} values")
+        full = np.ones((n + 1, n + 1))
+        if cfg.get("a0_boundary") is not None:
+            full[:] = np.asarray(cfg["a0_boundary"], dtype=np.float64).reshape(n + 1, n + 1)
+        full[1:n, 1:n] = a0_interior.detach().cpu().numpy().reshape(n - 1, n - 1)
+        prob = Problem(n, cfg["m"], cfg["p"], float(sigma), corr_len=cfg.get("corr_len", 0.5),
+                       a0_nodal=full.ravel(), kl_amp=amps.detach().cpu().numpy(),
                        coarsest=cfg.get("coarsest", 8))
         solve_kw = cfg.get("solve", {})
         U, _info = prob.solve(**solve_kw)
         J, _q = prob.qoi(U)
-        ctx.prob, ctx.U, ctx.solve_kw, ctx.n = prob, U, solve_kw, cfg["n"]
+        ctx.prob, ctx.U, ctx.solve_kw = prob, U, solve_kw
         return torch.tensor(J, dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, gout):
         g = ctx.prob.qoi_grad(ctx.U, **ctx.solve_kw)
-        n = ctx.n
-        da0 = torch.zeros((n + 1, n + 1), dtype=torch.float64)
-        da0[1:n, 1:n] = torch.from_numpy(g["da0"].reshape(n - 1, n - 1))
         ctx.prob.close()
         ctx.prob = ctx.U = None
         return (gout * torch.tensor(g["dsigma"], dtype=torch.float64),
-                gout * torch.from_numpy(g["damp"]), gout * da0.reshape(-1), None)
+                gout * torch.from_numpy(g["damp"]), gout * torch.from_numpy(g["da0"]), None)

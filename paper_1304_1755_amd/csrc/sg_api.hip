@@ -3,6 +3,7 @@
 // enqueues kernels on the context's stream and runs the O(restart^2) scalar
 // work of the Krylov recurrences (Hessenberg, Givens rotations).
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -31,6 +32,18 @@ int dalloc(sg_ctx* c, T** p, size_t count) {
     return SG_OK;
 }
 
+// free one allocation made by dalloc (no-op for null)
+void dfree(sg_ctx* c, void* q) {
+    if (!q) return;
+    for (size_t i = 0; i < c->allocations.size(); ++i)
+        if (c->allocations[i] == q) {
+            c->allocations.erase(c->allocations.begin() + i);
+            break;
+        }
+    (void)hipStreamSynchronize(c->stream);  // no queued kernel may still use it
+    (void)hipFree(q);
+}
+
 template <typename T>
 int upload(sg_ctx* c, T** p, const std::vector<T>& host) {
     int rc = dalloc(c, p, host.size());
@@ -46,8 +59,16 @@ int upload_plan(sg_ctx* c, const PlanHost& ph, Plan& pl) {
     pl.W_out = ph.W_out;
     pl.nslot = ph.nslot;
     pl.self = ph.self;
-    for (int s = 0; s < kMaxSlots; ++s) pl.mask[s] = s < (int)ph.mask.size() ? ph.mask[s] : 0u;
-    int rc = upload(c, &pl.d_off, ph.off);
+    if ((int)ph.npos.size() != ph.nslot) {
+        set_error("coupling plan: more partner positions than the apply kernel holds");
+        return SG_EINVAL;
+    }
+    pl.nblk_max = 0;
+    for (int v : ph.npos) pl.nblk_max = std::max(pl.nblk_max, (v + 3) / 4);
+    int rc = upload(c, &pl.d_xoff, ph.xoff);
+    if (!rc) rc = upload(c, &pl.d_xcoef, ph.xcoef);
+    if (!rc) rc = upload(c, &pl.d_npos, ph.npos);
+    if (!rc) rc = upload(c, &pl.d_off, ph.off);
     if (rc) return rc;
     return upload(c, &pl.d_coef, ph.coef);
 }
@@ -104,14 +125,27 @@ int ensure_krylov(sg_ctx* c, int restart, int z_float) {
         rc = dalloc(c, &c->ws.w, np);
         if (rc) return rc;
     }
+    // V holds restart + 1 double vectors; Z holds restart vectors of the
+    // preconditioner's precision.  A larger request replaces the old buffers
+    // (freed first, so growing does not strand device memory).
     if (c->ws.restart < restart) {
+        dfree(c, c->ws.V);
+        c->ws.V = nullptr;
+        c->ws.restart = 0;
         rc = dalloc(c, &c->ws.V, (size_t)(restart + 1) * NPpad(c));
         if (rc) return rc;
-        double* z = nullptr;  // sized for doubles, so it also holds a float basis
-        rc = dalloc(c, &z, (size_t)restart * NPpad(c));
+        c->ws.restart = restart;
+    }
+    const size_t zbytes = (size_t)restart * NPpad(c) * (z_float ? sizeof(float) : sizeof(double));
+    if (c->ws.z_bytes < zbytes) {
+        dfree(c, c->ws.Z);
+        c->ws.Z = nullptr;
+        c->ws.z_bytes = 0;
+        char* z = nullptr;
+        rc = dalloc(c, &z, zbytes);
         if (rc) return rc;
         c->ws.Z = z;
-        c->ws.restart = restart;
+        c->ws.z_bytes = zbytes;
     }
     c->ws.z_is_float = z_float;
     return SG_OK;
@@ -365,7 +399,7 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
         }
         if (k == 0) {
             set_error("FGMRES breakdown in the first step");
-            return SG_ENAN;
+            return SG_EBREAKDOWN;
         }
         // least squares min |beta e_0 - Hc y| by Givens rotations on the corrected columns
         std::vector<double> R((size_t)(k + 1) * k), gg(k + 1, 0.0);
@@ -444,6 +478,10 @@ int pcg(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_solve_
         SG_HIP_CHECK(vec_dot(c->stream, p, q, np, c->ws.partial, scal));
         if ((rc = fetch(c, scal, 1))) return rc;
         tm.collect(false, true, false);
+        if (!(hs[0] > 0.0) || !std::isfinite(hs[0])) {
+            set_error(std::isfinite(hs[0]) ? "PCG breakdown: (A p, p) <= 0" : "PCG curvature is not finite");
+            return std::isfinite(hs[0]) ? SG_EBREAKDOWN : SG_ENAN;
+        }
         const double alpha = rz / hs[0];
         SG_HIP_CHECK(vec_axpy(c->stream, alpha, p, X, np));
         SG_HIP_CHECK(vec_axpy_sq(c->stream, -alpha, q, r, np, c->ws.partial, scal));
@@ -510,6 +548,10 @@ int gpcg1(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_solv
         SG_HIP_CHECK(vec_dot(c->stream, r, p, np, c->ws.partial, scal + 1));
         if ((rc = fetch(c, scal, 2))) return rc;
         tm.collect(info.iters == 0, true, false);
+        if (!(hs[0] > 0.0) || !std::isfinite(hs[0])) {
+            set_error(std::isfinite(hs[0]) ? "GPCG breakdown: (A p, p) <= 0" : "GPCG curvature is not finite");
+            return std::isfinite(hs[0]) ? SG_EBREAKDOWN : SG_ENAN;
+        }
         const double pq = hs[0], alpha = hs[1] / pq;
         SG_HIP_CHECK(vec_axpy(c->stream, alpha, p, X, np));
         SG_HIP_CHECK(vec_axpy_sq(c->stream, -alpha, q, r, np, c->ws.partial, scal));
@@ -820,6 +862,12 @@ int sg_solve(sg_ctx* c, const double* F, double* U, const sg_solve_opts* opts, s
     std::memset(&info, 0, sizeof(info));
     Timer tm;
     tm.init(opts->timing != 0);
+    // work the caller queued earlier on the stream is not part of the solve's time
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        set_error("sg_solve: stream synchronisation failed before the solve");
+        tm.done();
+        return SG_EHIP;
+    }
     auto t0 = std::chrono::steady_clock::now();
     int rc;
     switch (opts->solver) {

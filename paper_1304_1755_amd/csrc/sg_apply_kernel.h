@@ -7,11 +7,11 @@
 //   * the lower coupling of the block-triangular sweep (Sec. 4.2):
 //       Y_d = R_d - sum_{k>=1} [G_k]_{d,d-1} (x) K_k U_{d-1}.
 //
-// Design (gfx950): one workgroup walks a segment of one grid row, one node
-// per step; its lanes (64 per wave, up to 4 waves) hold the P chaos modes of
-// that node, so every load of a node's mode vector is a contiguous, coalesced
-// access and the element coefficients around the node are wave-uniform
-// scalars, loaded once and reused by all modes.
+// Design (gfx950): one workgroup walks a segment of a pair of grid rows,
+// one node column per step; its lanes (64 per wave, up to 4 waves) hold the P
+// chaos modes of those nodes, so every load of a node's mode vector is a
+// contiguous, coalesced access and the element coefficients around the node
+// are wave-uniform scalars, loaded once and reused by all modes.
 // Bilinear elements (TRI = false): with cell-constant coefficients, K_k u at
 // a node is sum over the four cells of c_{k,e} r_e, where r_e = 4u_c - (two
 // edge neighbours in that cell) - 2 (opposite corner) is the node's row of
@@ -20,10 +20,13 @@
 // K_k u at a node is sum over its four grid edges of w_{k,e} (u_c - u_e).
 // The per-node differences are computed once per mode and shared by all m+1
 // stencils.  The G_k coupling (alpha <-> alpha +- e_k, Sec. 3.2) crosses
-// lanes: each lane writes its K_k u (k >= 1) to an LDS exchange buffer and
-// reads back the entries of its coupling partners through precomputed
-// index/coefficient tables held in registers.  A 3x3 window of mode vectors
-// slides along the row, so each step loads one new column.
+// lanes: each lane writes its K_k u (k >= 1) to an LDS exchange buffer, two k
+// per 128-bit store, and reads back its coupling partners.  The partners of
+// a lane are listed by the value of their coefficient G_k(alpha, beta), which
+// takes only p values: inside one wavefront every list position then has one
+// coefficient for all lanes, held in scalar registers, and only the partner
+// indices (16 bits each) stay in vector registers.  A 3x4 window of mode
+// vectors slides along the rows, so each step loads one new column.
 //
 // This header holds the kernel and its launchers; each discretisation is
 // instantiated in a translation unit of its own.
@@ -65,21 +68,20 @@ __device__ __forceinline__ void unroll_steps(F&& f, std::integer_sequence<int, J
 // segment.  Per column, every wave writes the K_k u (k >= 1) of its RW nodes
 // into a block-shared LDS exchange buffer, the workgroup meets at a barrier,
 // and every wave then gathers its coupling partners from the whole buffer.
-// Splitting the modes over waves keeps each wave's coupling tables and
-// window small, so several workgroups share a CU and hide memory latency;
-// two rows per workgroup share the window's middle rows and the cell row
-// between them, and halve the synchronizations per node.
+// Splitting the modes over waves keeps each wave's window and partner lists
+// small, so several workgroups share a CU and hide memory latency; two rows
+// per workgroup share the window's middle rows and the cell row between them,
+// and halve the synchronizations per node.
 template <int M, int NS, int RW, typename Tin, typename Tout, bool HAS_R, bool TRI>
 __global__ void __launch_bounds__(NS * 64)
 k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int ldr,
            Tout* __restrict__ Y, int ldy, const double* __restrict__ cell,
-           const uint32_t* __restrict__ toff, const double* __restrict__ tcoef, int n, int W_in,
-           int W_out, int self, const Tin* __restrict__ zin, int seg, int nseg) {
+           const uint32_t* __restrict__ xoff, const double* __restrict__ xcoef, const int* __restrict__ npos_slot,
+           int n, int W_in, int W_out, int self, const Tin* __restrict__ zin, int seg, int nseg) {
     constexpr int MM = M > 0 ? M : 1;
     constexpr int LANES = NS * 64;
-    constexpr int NODE = MM * LANES + 2;      // exchange entries of one node (+ its zero entry)
-    constexpr int NBUF = RW == 1 ? 2 : 1;      // one row: double-buffered by column parity
-    __shared__ double S[NBUF][RW * NODE];
+    constexpr int NODE = MM * LANES + 2;  // exchange entries of one node (+ its zero entry; even: 16-byte rows)
+    __shared__ __attribute__((aligned(16))) double S[RW * NODE];
     const int lane = threadIdx.x & 63;
     const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wave's slot (uniform)
     const int nx = n - 1;
@@ -96,29 +98,26 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     const int t = s * 64 + lane;
     const bool has_out = s * 64 < W_out;  // uniform
     const bool vin = t < W_in, vout = t < W_out;
-
-    // this lane's partners: position 2k = alpha + e_k, 2k+1 = alpha - e_k
-    uint32_t off[MM];
-    double ce[2 * MM];
+    // this lane's partner list (16-bit exchange indices) and the slot's
+    // per-position coefficients (uniform) and number of used positions
+    const int npos = __builtin_amdgcn_readfirstlane(npos_slot[s]);
+    const double* cw = xcoef + s * kNPos;
+    uint32_t off[kNPos / 2];
 #pragma unroll
-    for (int j = 0; j < MM; ++j) {
-        off[j] = M > 0 ? toff[t * MM + j] : 0u;
-        ce[2 * j] = M > 0 ? tcoef[t * 2 * MM + 2 * j] : 0.0;
-        ce[2 * j + 1] = M > 0 ? tcoef[t * 2 * MM + 2 * j + 1] : 0.0;
-    }
-    if (threadIdx.x < RW * NBUF) S[threadIdx.x / RW][(threadIdx.x % RW) * NODE + MM * LANES] = 0.0;  // zero entries
+    for (int j = 0; j < kNPos / 2; ++j) off[j] = xoff[t * (kNPos / 2) + j];
+    if (threadIdx.x < RW) S[threadIdx.x * NODE + MM * LANES] = 0.0;  // zero entries
 
     // Circular window wb[row][c] of mode vectors, rows y0-1 .. y0+RW: column
     // x of the grid lives in wb[.][(x - x0 + 1) mod C].  Step x reads columns
     // x-1, x, x+1 and issues the loads of column x+1+D, so D columns are in
     // flight while earlier steps compute; the walk is unrolled by C, which
-    // makes every column role, the R slot and the LDS buffer parity a
-    // compile-time constant and the window needs no register moves.  A
-    // neighbour outside the grid is read from the zero vector zin (a
-    // wave-uniform choice of base pointer, so no per-value select), and lanes
-    // past W_in read a valid column: their values feed no partner.
-    constexpr int C = RW == 1 ? 8 : 6;
-    constexpr int D = C - 3;  // columns in flight; D + 3 columns are live
+    // makes every column role and the R slot a compile-time constant and the
+    // window needs no register moves.  A neighbour outside the grid is read
+    // from the zero vector zin (a wave-uniform choice of base pointer, so no
+    // per-value select), and lanes past W_in read a valid column: their
+    // values feed no partner.
+    constexpr int C = 4;
+    constexpr int D = C - 3;  // columns in flight
     constexpr int NR = RW + 2;
     const uint32_t tci = vin ? t : W_in - 1;
     const uint32_t tco = vout ? t : W_out - 1;
@@ -174,7 +173,6 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     auto step = [&](auto kstep, int x) {
         constexpr int j = decltype(kstep)::value;  // x - x0 mod C
         constexpr int cW = j % C, cC = (j + 1) % C, cE = (j + 2) % C, cL = (j + 2 + D) % C;
-        double* B = S[NBUF == 2 ? (j & 1) : 0];
         double rv[RW];
 #pragma unroll
         for (int q = 0; q < RW; ++q) rv[q] = HAS_R ? qr[q][j % D] : 0.0;
@@ -185,9 +183,21 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
         for (int q = 0; q < RW; ++q) {
             s0[q] = 0.0;
             if (RW > 1 && y0 + q >= nx) break;  // uniform: no such row (its cells would lie outside)
+            double* Bq = S + q * NODE;
             const double wS = (double)wb[q][cC];
             const double wW = (double)wb[q + 1][cW], wc = (double)wb[q + 1][cC], wE = (double)wb[q + 1][cE];
             const double wN = (double)wb[q + 2][cC];
+            // K_k u of this node for k = 1..M into the exchange row, pairs of k per 128-bit store
+            auto put = [&](auto stencil) {
+#pragma unroll
+                for (int kk = 0; kk < 2 * (M / 2); kk += 2) {
+                    double2 v;
+                    v.x = stencil(kk + 1);
+                    v.y = stencil(kk + 2);
+                    *(double2*)(Bq + exchange_index(M, LANES, kk, t)) = v;
+                }
+                if constexpr ((M & 1) != 0) Bq[exchange_index(M, LANES, M - 1, t)] = stencil(M);
+            };
             if constexpr (TRI) {
                 // node (x, y0 + q) is grid vertex (x+1, y0+q+1); 2(M+1) weights per vertex:
                 // its east edges for k = 0..M, then its north edges.  West edge = east
@@ -198,29 +208,28 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
                 const double* pS = crow[q] + (x + 1) * CW + (M + 1);
                 const double* pN = pC + (M + 1);
                 const double dE = wc - wE, dW = wc - wW, dN = wc - wN, dS = wc - wS;
-                s0[q] = fma(pC[0], dE, fma(pW[0], dW, fma(pN[0], dN, pS[0] * dS)));
-#pragma unroll
-                for (int kk = 1; kk <= M; ++kk)
-                    B[q * NODE + (kk - 1) * LANES + t] = fma(pC[kk], dE, fma(pW[kk], dW, fma(pN[kk], dN, pS[kk] * dS)));
-                continue;
+                auto stencil = [&](int kk) { return fma(pC[kk], dE, fma(pW[kk], dW, fma(pN[kk], dN, pS[kk] * dS))); };
+                s0[q] = stencil(0);
+                put(stencil);
+            } else {
+                // node (x, y0 + q); cells SW (x, y0+q), SE (x+1, y0+q), NW (x, y0+q+1), NE (x+1, y0+q+1)
+                const double wSW = (double)wb[q][cW], wSE = (double)wb[q][cE];
+                const double wNW = (double)wb[q + 2][cW], wNE = (double)wb[q + 2][cE];
+                const double* cSW = crow[q] + x * (M + 1);
+                const double* cSE = cSW + (M + 1);
+                const double* cNW = crow[q + 1] + x * (M + 1);
+                const double* cNE = cNW + (M + 1);
+                const double uc4 = 4.0 * wc;
+                const double rSW = fma(-2.0, wSW, uc4 - (wS + wW));
+                const double rSE = fma(-2.0, wSE, uc4 - (wS + wE));
+                const double rNW = fma(-2.0, wNW, uc4 - (wN + wW));
+                const double rNE = fma(-2.0, wNE, uc4 - (wN + wE));
+                auto stencil = [&](int kk) {
+                    return fma(cSW[kk], rSW, fma(cSE[kk], rSE, fma(cNW[kk], rNW, cNE[kk] * rNE)));
+                };
+                s0[q] = stencil(0);
+                put(stencil);
             }
-            // node (x, y0 + q); cells SW (x, y0+q), SE (x+1, y0+q), NW (x, y0+q+1), NE (x+1, y0+q+1)
-            const double wSW = (double)wb[q][cW], wSE = (double)wb[q][cE];
-            const double wNW = (double)wb[q + 2][cW], wNE = (double)wb[q + 2][cE];
-            const double* cSW = crow[q] + x * (M + 1);
-            const double* cSE = cSW + (M + 1);
-            const double* cNW = crow[q + 1] + x * (M + 1);
-            const double* cNE = cNW + (M + 1);
-            const double uc4 = 4.0 * wc;
-            const double rSW = fma(-2.0, wSW, uc4 - (wS + wW));
-            const double rSE = fma(-2.0, wSE, uc4 - (wS + wE));
-            const double rNW = fma(-2.0, wNW, uc4 - (wN + wW));
-            const double rNE = fma(-2.0, wNE, uc4 - (wN + wE));
-            s0[q] = fma(cSW[0], rSW, fma(cSE[0], rSE, fma(cNW[0], rNW, cNE[0] * rNE)));
-#pragma unroll
-            for (int kk = 1; kk <= M; ++kk)
-                B[q * NODE + (kk - 1) * LANES + t] =
-                    fma(cSW[kk], rSW, fma(cSE[kk], rSE, fma(cNW[kk], rNW, cNE[kk] * rNE)));
         }
         // LDS writes done, then the block barrier (no global-memory wait: the
         // window loads stay in flight)
@@ -232,25 +241,30 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
 #pragma unroll
             for (int q = 0; q < RW; ++q) {
                 if (RW > 1 && y0 + q >= nx) break;  // uniform: the last row pair of an odd grid
-                const double* Bq = B + q * NODE;
-                double acc = self ? s0[q] : 0.0;
+                const double* Bq = S + q * NODE;
+                double acc0 = self ? s0[q] : 0.0, acc1 = 0.0;
+                // blocks of four positions; a block past the slot's last used
+                // position is skipped for the whole wave
 #pragma unroll
-                for (int jj = 0; jj < M; ++jj) {
-                    // absent partners read the node's zero entry: unconditional
-                    // gathers schedule better than skipping positions per wave
-                    acc = fma(ce[2 * jj], Bq[off[jj] & 0xFFFFu], acc);
-                    acc = fma(ce[2 * jj + 1], Bq[off[jj] >> 16], acc);
+                for (int blk = 0; blk < kNPos / 4; ++blk) {
+                    if (blk * 4 < npos) {
+                        const double v0 = Bq[off[2 * blk] & 0xFFFFu], v1 = Bq[off[2 * blk] >> 16];
+                        const double v2 = Bq[off[2 * blk + 1] & 0xFFFFu], v3 = Bq[off[2 * blk + 1] >> 16];
+                        acc0 = fma(cw[4 * blk], v0, acc0);
+                        acc1 = fma(cw[4 * blk + 1], v1, acc1);
+                        acc0 = fma(cw[4 * blk + 2], v2, acc0);
+                        acc1 = fma(cw[4 * blk + 3], v3, acc1);
+                    }
                 }
+                const double acc = acc0 + acc1;
                 if (vout) st_from_double(yrow[q] + (size_t)x * ldy + t, HAS_R ? rv[q] - acc : acc);
             }
         }
-        if (NBUF == 1) {
-            // single buffer: every wave has gathered before the next column is written
-            __builtin_amdgcn_s_waitcnt(0xC07F);
-            __asm__ __volatile__("" ::: "memory");
-            __builtin_amdgcn_s_barrier();
-            __asm__ __volatile__("" ::: "memory");
-        }
+        // every wave has gathered before the next column is written
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        __asm__ __volatile__("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        __asm__ __volatile__("" ::: "memory");
     };
     for (int x = x0; x < x1; x += C) {
         // x, x1 are uniform, so every wave of the block meets the same barriers
@@ -276,12 +290,12 @@ hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, cons
     const int blocks = (nx + RW - 1) / RW * nseg;
     if (R)
         hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, true, TRI>), dim3(blocks), dim3(NS * 64), 0, st,
-                           (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out,
-                           pl.self, (const Tin*)zin, seg, nseg);
+                           (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_xoff, pl.d_xcoef, pl.d_npos, n, pl.W_in,
+                           pl.W_out, pl.self, (const Tin*)zin, seg, nseg);
     else
         hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, false, TRI>), dim3(blocks), dim3(NS * 64), 0, st,
-                           (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_off, pl.d_coef, n, pl.W_in, pl.W_out,
-                           pl.self, (const Tin*)zin, seg, nseg);
+                           (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_xoff, pl.d_xcoef, pl.d_npos, n, pl.W_in,
+                           pl.W_out, pl.self, (const Tin*)zin, seg, nseg);
     return hipGetLastError();
 }
 

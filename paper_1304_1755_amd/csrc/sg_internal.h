@@ -53,23 +53,45 @@ struct HostSetup {
 int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_amp, HostSetup& hs);
 
 // coupling tables of one apply "plan": output modes [out_lo, out_lo+W_out),
-// input modes [in_lo, in_lo+W_in).  For each output lane and k: the LDS
-// element indices of the partners alpha + e_k (low 16 bits) and alpha - e_k
-// (high 16 bits) and their coefficients G_k(alpha, beta) at positions 2k and
-// 2k+1; mask[s] marks the positions used by any lane of slot s.
+// input modes [in_lo, in_lo+W_in).  Lanes are grouped in slots of 64 (one
+// wavefront each); the K_k u values (k >= 1) of a node row are exchanged
+// through LDS at element exchange_index(k - 1, input lane).
+//   Apply tables: every output lane lists its coupling partners at kNPos
+//   positions (16-bit exchange indices, two per word; an absent partner reads
+//   the row's zero entry).  Positions are grouped by the value of the
+//   coefficient G_k(alpha, beta), so that inside one slot every position has a
+//   single coefficient, shared by all lanes: xcoef[slot][position], and the
+//   slot uses the first npos[slot] positions.
+//   Gradient tables (full plan, read by the adjoint cell-gradient kernel):
+//   for each lane and k, the partners alpha + e_k (low 16 bits of off) and
+//   alpha - e_k (high 16 bits) as element k*lanes + beta, with coefficients
+//   at positions 2k and 2k+1 of coef.
+constexpr int kNPos = 16;
+
+__host__ __device__ constexpr int exchange_index(int m, int lanes, int kk, int b) {
+    // K_{kk+1} u of input lane b: pairs of consecutive k share one 16-byte slot
+    // per lane (written with one 128-bit store); an odd last k stands alone
+    return kk < 2 * (m / 2) ? (kk >> 1) * 2 * lanes + 2 * b + (kk & 1) : 2 * (m / 2) * lanes + b;
+}
+
 struct PlanHost {
     int in_lo = 0, W_in = 0, out_lo = 0, W_out = 0, nslot = 1;
     int self = 0;  // include the k = 0 (G_0 = I) term
-    std::vector<uint32_t> off;   // nslot*64*m
-    std::vector<double> coef;    // nslot*64*2m
-    std::vector<uint32_t> mask;  // nslot
+    std::vector<uint32_t> xoff;   // nslot*64*kNPos/2
+    std::vector<double> xcoef;    // nslot*kNPos
+    std::vector<int> npos;        // nslot
+    std::vector<uint32_t> off;    // nslot*64*m   (gradient tables)
+    std::vector<double> coef;     // nslot*64*2m
 };
 PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_out, bool self, bool up, bool down);
 
 // ---------------------------------------------------------------- device side
 struct Plan {
     int in_lo, W_in, out_lo, W_out, nslot, self;
-    uint32_t mask[kMaxSlots];
+    uint32_t* d_xoff;
+    double* d_xcoef;
+    int* d_npos;
+    int nblk_max;  // max over slots of ceil(npos / 4)
     uint32_t* d_off;
     double* d_coef;
 };
@@ -88,6 +110,7 @@ struct Workspace {
     int restart = 0;
     double* V = nullptr;         // (restart+1) x NP
     void* Z = nullptr;           // restart x NP, float (mixed) or double
+    size_t z_bytes = 0;          // capacity of Z in bytes
     int z_is_float = 0;
     double* w = nullptr;         // NP
     double* amps = nullptr;      // m KL amplitudes s_k

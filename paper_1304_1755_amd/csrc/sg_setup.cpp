@@ -411,13 +411,6 @@ int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_a
 }
 
 PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_out, bool self, bool up, bool down) {
-    // Fixed positions per lane: entry 2k is the partner alpha + e_k, entry
-    // 2k+1 the partner alpha - e_k, each as (LDS element k*lanes + beta,
-    // G_k(alpha, beta)), or the shared zero entry when absent.  Keeping the
-    // positions aligned across lanes keeps the gathers close to contiguous.
-    // mask[s] has bit i set when some lane of slot s has entry i, so a wave
-    // skips positions that are empty for all its lanes (e.g. the up partners
-    // of the top degree level).
     PlanHost pl;
     pl.in_lo = in_lo;
     pl.W_in = W_in;
@@ -427,13 +420,16 @@ PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_o
     pl.nslot = std::max((W_in + 63) / 64, (W_out + 63) / 64);
     if (pl.nslot < 1) pl.nslot = 1;
     const int m = hs.m, lanes = pl.nslot * 64, L = 2 * std::max(m, 1);
-    const uint32_t zero = (uint32_t)(m * lanes);
-    pl.off.assign((size_t)lanes * (L / 2), zero | (zero << 16));
-    pl.coef.assign((size_t)lanes * L, 0.0);
-    pl.mask.assign(pl.nslot, 0u);
     std::map<std::vector<int>, int> pos;
     for (int a = 0; a < hs.P; ++a)
         pos[std::vector<int>(hs.midx.begin() + (size_t)a * m, hs.midx.begin() + (size_t)(a + 1) * m)] = a;
+    // the partners of every output lane: (k, direction, input lane, coefficient key n),
+    // where G_k(alpha, beta) = gscale * b_n with n = alpha_k + 1 for the up partner
+    // alpha + e_k and n = alpha_k for the down partner alpha - e_k
+    struct Partner {
+        int k, dir, b, key;
+    };
+    std::vector<std::vector<Partner>> parts(lanes);
     for (int t = 0; t < W_out; ++t) {
         const int a = out_lo + t;
         std::vector<int> al(hs.midx.begin() + (size_t)a * m, hs.midx.begin() + (size_t)(a + 1) * m);
@@ -444,15 +440,56 @@ PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_o
                 b[k] += dir == 0 ? 1 : -1;
                 auto it = pos.find(b);
                 if (it == pos.end() || it->second < in_lo || it->second >= in_lo + W_in) continue;
-                // E[xi q_a q_{a+1}] = b_{a+1}: up partner uses a = alpha_k, down partner a = alpha_k - 1
-                const double g = hs.gscale * (dir == 0 ? legendre_b(al[k] + 1) : legendre_b(al[k]));
-                const uint32_t idx = (uint32_t)(k * lanes + (it->second - in_lo));
-                uint32_t& w = pl.off[(size_t)t * (L / 2) + k];
-                if (dir == 0) w = (w & 0xFFFF0000u) | idx;
-                else w = (w & 0x0000FFFFu) | (idx << 16);
-                pl.coef[(size_t)t * L + 2 * k + dir] = g;
-                pl.mask[t / 64] |= 1u << (2 * k + dir);
+                parts[t].push_back({k, dir, it->second - in_lo, dir == 0 ? al[k] + 1 : al[k]});
             }
+    }
+    // gradient tables: fixed positions 2k (up) and 2k+1 (down) per lane
+    const uint32_t gzero = (uint32_t)(m * lanes);
+    pl.off.assign((size_t)lanes * (L / 2), gzero | (gzero << 16));
+    pl.coef.assign((size_t)lanes * L, 0.0);
+    for (int t = 0; t < lanes; ++t)
+        for (const Partner& q : parts[t]) {
+            const uint32_t idx = (uint32_t)(q.k * lanes + q.b);
+            uint32_t& w = pl.off[(size_t)t * (L / 2) + q.k];
+            w = q.dir == 0 ? ((w & 0xFFFF0000u) | idx) : ((w & 0x0000FFFFu) | (idx << 16));
+            pl.coef[(size_t)t * L + 2 * q.k + q.dir] = hs.gscale * legendre_b(q.key);
+        }
+    // apply tables: per slot, the positions are grouped by coefficient key
+    // (ascending); a key takes as many positions as the slot's lane with the
+    // most partners of that key needs
+    const uint32_t xzero = (uint32_t)(std::max(m, 1) * lanes);
+    pl.xoff.assign((size_t)lanes * (kNPos / 2), xzero | (xzero << 16));
+    pl.xcoef.assign((size_t)pl.nslot * kNPos, 0.0);
+    pl.npos.assign(pl.nslot, 0);
+    for (int s = 0; s < pl.nslot; ++s) {
+        std::map<int, int> width;
+        for (int t = 64 * s; t < 64 * s + 64; ++t) {
+            std::map<int, int> cnt;
+            for (const Partner& q : parts[t]) cnt[q.key]++;
+            for (const auto& kv : cnt) width[kv.first] = std::max(width[kv.first], kv.second);
+        }
+        std::map<int, int> start;
+        int np = 0;
+        for (const auto& kv : width) {
+            start[kv.first] = np;
+            for (int i = 0; i < kv.second && np + i < kNPos; ++i)
+                pl.xcoef[(size_t)s * kNPos + np + i] = hs.gscale * legendre_b(kv.first);
+            np += kv.second;
+        }
+        if (np > kNPos) {  // cannot happen for P <= 256 (at most 14 positions); refuse rather than truncate
+            pl.npos.clear();
+            return pl;
+        }
+        pl.npos[s] = np;
+        for (int t = 64 * s; t < 64 * s + 64; ++t) {
+            std::map<int, int> used;
+            for (const Partner& q : parts[t]) {
+                const int j = start[q.key] + used[q.key]++;
+                const uint32_t idx = (uint32_t)exchange_index(m, lanes, q.k, q.b);
+                uint32_t& w = pl.xoff[(size_t)t * (kNPos / 2) + j / 2];
+                w = (j & 1) ? ((w & 0x0000FFFFu) | (idx << 16)) : ((w & 0xFFFF0000u) | idx);
+            }
+        }
     }
     return pl;
 }

@@ -31,6 +31,31 @@ def test_gradient_matches_oracle_small():
     g.close()
 
 
+def test_gradient_matches_oracle_c5():
+    # the adjoint workload itself (257^2, m = 5, p = 3, P = 56, sigma = 0.3, seeded a0 noise): every
+    # component of the GPU gradient (dJ/dsigma, the 5 dJ/ds_k and all 65,025 interior dJ/da0)
+    # against the oracle's adjoint gradient (direct solves), element by element
+    import paper_1304_1755_amd as sgbt
+    note("adjoint c5 vs oracle gradient")
+    cfg = sg_inputs.CONFIGS["c5"]
+    n, m, p = cfg["n"], cfg["m"], cfg["p"]
+    a0 = sg_inputs.a0_noise_field(n)
+    g = sgbt.Problem(n, m, p, cfg["sigma"], cfg["corr_len"], a0_nodal=a0)
+    U, info = g.solve(**FIXED)
+    gr = g.qoi_grad(U, **FIXED)
+    g.close()
+    note(f"c5 gpu: J {gr['J']:.15e}, forward {info['iters']} it, adjoint {gr['adj_info']['iters']} it")
+    o = system.build_problem(n, m, p, cfg["sigma"], cfg["corr_len"], a0_nodal=a0)
+    ref = qoi.qoi_and_gradient(o)
+    note(f"c5 oracle: J {ref['J']:.15e}")
+    assert abs(gr["J"] - ref["J"]) < 1e-10 * abs(ref["J"])
+    assert abs(gr["dsigma"] - ref["dsigma"]) < 1e-8 * abs(ref["dsigma"])
+    assert np.max(np.abs(gr["damp"] - ref["damp"])) < 1e-8 * np.max(np.abs(ref["damp"]))
+    err_a0 = np.max(np.abs(gr["da0"] - ref["da0"])) / np.max(np.abs(ref["da0"]))
+    note(f"c5 gradient: max rel error of dJ/da0 {err_a0:.2e}")
+    assert err_a0 < 1e-8
+
+
 # Finite differences of J need J to be a smooth function of the parameters.
 # At 257^2 the relative residual cannot go below about 1e-11 (rounding in
 # A U ~ F with |A||U| >> |F|), so a tolerance-driven stop would make the
@@ -101,18 +126,42 @@ def test_gradient_against_central_differences_c5():
 
 
 def test_autograd_function():
+    # the interior nodal values of a0 are the differentiable input; the boundary
+    # vertices are data (here 1); every input gets the oracle's gradient
     import paper_1304_1755_amd as sgbt
     note("autograd function")
     n, m, p = 16, 2, 2
-    o = system.build_problem(n, m, p, 0.3)
+    a0 = sg_inputs.a0_noise_field(n)
+    o = system.build_problem(n, m, p, 0.3, a0_nodal=a0)
     sigma = torch.tensor(0.3, dtype=torch.float64, requires_grad=True)
     amps = torch.tensor(o.kldata["amps"], dtype=torch.float64, requires_grad=True)
-    a0 = torch.ones((n + 1) ** 2, dtype=torch.float64, requires_grad=True)
-    J = sgbt.SGQoI.apply(sigma, amps, a0, dict(n=n, m=m, p=p, solve=SOLVE))
+    inner = torch.tensor(a0.reshape(n + 1, n + 1)[1:n, 1:n].ravel(), dtype=torch.float64, requires_grad=True)
+    J = sgbt.SGQoI.apply(sigma, amps, inner, dict(n=n, m=m, p=p, a0_boundary=a0, solve=SOLVE))
     J.backward()
     ref = qoi.qoi_and_gradient(o)
     assert abs(J.item() - ref["J"]) < 1e-11 * abs(ref["J"])
     assert abs(sigma.grad.item() - ref["dsigma"]) < 1e-8 * max(1, abs(ref["dsigma"]))
-    ga0 = a0.grad.reshape(n + 1, n + 1)[1:n, 1:n].reshape(-1).numpy()
-    assert np.max(np.abs(ga0 - ref["da0"])) < 1e-8 * np.max(np.abs(ref["da0"]))
-    assert torch.all(a0.grad.reshape(n + 1, n + 1)[0] == 0)
+    assert np.max(np.abs(amps.grad.numpy() - ref["damp"])) < 1e-8 * max(1, np.max(np.abs(ref["damp"])))
+    assert np.max(np.abs(inner.grad.numpy() - ref["da0"])) < 1e-8 * np.max(np.abs(ref["da0"]))
+
+
+def test_boundary_a0_is_data_not_a_parameter():
+    # a0 on the boundary vertices changes J (the cells next to the boundary average it in), so it
+    # cannot silently receive a zero gradient: the autograd Function takes it as fixed data
+    import paper_1304_1755_amd as sgbt
+    note("boundary a0 is data")
+    n, m, p = 16, 2, 2
+    a0 = sg_inputs.a0_noise_field(n)
+    inner = torch.tensor(a0.reshape(n + 1, n + 1)[1:n, 1:n].ravel(), dtype=torch.float64)
+    amps = torch.tensor(system.build_problem(n, m, p, 0.3).kldata["amps"], dtype=torch.float64)
+    cfg = dict(n=n, m=m, p=p, solve=SOLVE)
+    J1 = sgbt.SGQoI.apply(torch.tensor(0.3, dtype=torch.float64), amps, inner, cfg).item()
+    bnd = np.full((n + 1) ** 2, 1.5)
+    J2 = sgbt.SGQoI.apply(torch.tensor(0.3, dtype=torch.float64), amps, inner, dict(cfg, a0_boundary=bnd)).item()
+    full = a0.reshape(n + 1, n + 1).copy()
+    full[0, :] = full[-1, :] = full[:, 0] = full[:, -1] = 1.5
+    ref = qoi.qoi_and_gradient(system.build_problem(n, m, p, 0.3, a0_nodal=full.ravel()))
+    assert abs(J2 - ref["J"]) < 1e-11 * abs(ref["J"])
+    assert abs(J1 - J2) > 1e-6 * abs(J1)
+    with pytest.raises(ValueError):
+        sgbt.SGQoI.apply(torch.tensor(0.3, dtype=torch.float64), amps, torch.ones((n + 1) ** 2, dtype=torch.float64), cfg)

@@ -122,3 +122,20 @@ def test_cell_coefficients_respect_mode_parity(n, m):
         assert np.allclose(f[:, ::-1], sx * f, atol=1e-15, rtol=1e-13)
         assert np.allclose(f[::-1, :], sy * f, atol=1e-15, rtol=1e-13)
         assert np.max(np.abs(f)) > 0.05
+
+
+def test_cell_coefficients_reproduce_the_covariance():
+    # Mercer: sum_k (sigma s_k b_k(x)) (sigma s_k b_k(y)) with s_k = sqrt(lambda_k) tends to the
+    # covariance sigma^2 exp(-|x1 - y1|/L - |x2 - y2|/L) (Sec. 2.1, eq. (exponential-covariance),
+    # separable reading).  Truncated after m modes the error is at most
+    # sigma^2 max_k |b_k|^2 sum_{k>m} lambda_k <= 4 sigma^2 (1 - sum_{k<=m} lambda_k), since every
+    # 1-D eigenfunction is bounded by sqrt 2 and the 1-D eigenvalues sum to one.  A wrong
+    # amplitude (lambda for sqrt lambda, a stray factor) or normalisation breaks the limit.
+    n, m, sigma, L = 4, 1000, 0.7, 0.5
+    c, data = fem.cell_coefficients(n, m, sigma, L)
+    cov = c[1:].T @ c[1:]
+    x1, x2 = fem.cell_centres(n)
+    ref = sigma ** 2 * np.exp(-(np.abs(x1[:, None] - x1[None, :]) + np.abs(x2[:, None] - x2[None, :])) / L)
+    bound = 4 * sigma ** 2 * (1.0 - data["lams"].sum())
+    assert bound < 0.05 * sigma ** 2
+    assert np.max(np.abs(cov - ref)) <= bound

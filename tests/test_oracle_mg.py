@@ -54,6 +54,25 @@ def test_colour_sweep_matches_scalar_loops(mode):
     assert np.max(np.abs(bwd - _brute_gs(K, f, u0, groups[::-1], mode == "rb"))) < 1e-13
 
 
+def test_lexicographic_sweep_matches_scalar_loops():
+    # lexicographic point Gauss-Seidel (nodes x-fastest, one at a time): forward in node order
+    # before the coarse correction, backward in reverse node order after it
+    n = 8
+    rng = np.random.default_rng(11)
+    K = fem.assemble_stiffness(n, rng.uniform(0.5, 2.0, n * n))
+    H = mg.Hierarchy(K, n, coarsest=8, colour_mode="lex")
+    N = (n - 1) ** 2
+    f = rng.standard_normal(N)
+    u0 = rng.standard_normal(N)
+    singles = [[i] for i in range(N)]
+    fwd = H.smooth(0, u0.copy(), f, reverse=False)
+    assert np.max(np.abs(fwd - _brute_gs(K, f, u0, singles, False))) < 1e-13
+    bwd = H.smooth(0, u0.copy(), f, reverse=True)
+    assert np.max(np.abs(bwd - _brute_gs(K, f, u0, singles[::-1], False))) < 1e-13
+    # a plausible slip, the wrong direction, is caught
+    assert np.max(np.abs(bwd - fwd)) > 1e-3
+
+
 def test_four_colours_never_touch():
     n = 10
     K = fem.assemble_stiffness(n, np.ones(n * n)).toarray()
