@@ -191,6 +191,20 @@ int sg_solve(sg_ctx* ctx, const double* F, double* U, const sg_solve_opts* opts,
  * U: device doubles.  q: host, P doubles (may be NULL).  J: host. */
 int sg_qoi(sg_ctx* ctx, const double* U, double* q, double* J);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): sg_qoi with
+ * no allocation at all.  Its scratch (reduction partials and adjoint weights)
+ * is a static per-device array of 1024 * 256 + 256 doubles (2 MiB), held by
+ * every GPU the library runs on until the process ends, and its results stay
+ * on the device.  U: device doubles, N x P.  q: device, P doubles (q_a).
+ * J: device, 1 double.  Enqueued on the context's stream; returns without
+ * waiting.  SG_DISC_Q1 only.  SG_EINVAL for null pointers, SG_DISC_P1, or a P
+ * whose partials exceed the array (cannot happen for P <= 256).  All calls on
+ * one GPU share the array: calls that overlap in time (any contexts, any
+ * streams) race; serialize them.  Nothing needs clearing between calls (every
+ * scratch entry is written before it is read). */
+int sg_qoi_noalloc(sg_ctx* ctx, const double* U, double* q, double* J);
+
 /* SG_DISC_Q1 only (SG_EINVAL otherwise).
  * Adjoint gradient of J at the solution U: solves A lambda = dJ/dU with the
  * same solver options, then dJ/dc_{k,e} = -sum G_k(a,b) lambda_{a,e}^T K_ref U_{b,e}

@@ -25,7 +25,7 @@ SG_DISC_Q1, SG_DISC_P1 = 0, 1
 DISCRETIZATIONS = {"q1": SG_DISC_Q1, "p1": SG_DISC_P1}
 
 EXPORTED = ["sg_setup", "sg_query", "sg_get_cell_coeffs", "sg_rhs", "sg_apply", "sg_residual", "sg_vcycle",
-            "sg_precond_diag", "sg_precond_tri", "sg_precond_sym", "sg_solve", "sg_qoi", "sg_qoi_grad",
+            "sg_precond_diag", "sg_precond_tri", "sg_precond_sym", "sg_solve", "sg_qoi", "sg_qoi_noalloc", "sg_qoi_grad",
             "sg_setup_host", "sg_sync",
             "sg_destroy", "sg_last_error"]
 
@@ -83,6 +83,7 @@ def load_library():
         "sg_precond_sym": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "sg_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
         "sg_qoi": (ctypes.c_int, [vp, vp, dp, dp]),
+        "sg_qoi_noalloc": (ctypes.c_int, [vp, vp, vp, vp]),
         "sg_qoi_grad": (ctypes.c_int, [vp, vp, ctypes.POINTER(SolveOpts), dp, dp, dp, dp,
                                        ctypes.POINTER(SolveInfo)]),
         "sg_setup_host": (ctypes.c_int, [ctypes.POINTER(Options), dp, dp, dp, dp, dp, dp, dp, dp]),
@@ -264,6 +265,12 @@ class Problem:
         _check(load_library().sg_qoi(self._ctx, self._t(U, torch.float64, (self.N, self.P)),
                                      q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(J)))
         return J.value, q
+
+    def qoi_noalloc(self, U, q, J):
+        """sg_qoi_noalloc: q (P) and J (1) are float64 device tensors the caller owns."""
+        _check(load_library().sg_qoi_noalloc(self._ctx, self._t(U, torch.float64, (self.N, self.P)),
+                                             self._t(q, torch.float64, (self.P,)), self._t(J, torch.float64, (1,))))
+        return q, J
 
     def qoi_grad(self, U, **kw):
         import numpy as np

@@ -699,6 +699,14 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
         set_error("sg_setup: no HIP device");
         return fail(SG_EHIP);
     }
+    {
+        // device address of the allocation-free QoI's scratch array (once per device)
+        const hipError_t e = qoi_scratch_address(c->device, &c->qoi_scratch);
+        if (e != hipSuccess) {
+            set_error(std::string("sg_setup: scratch address lookup failed: ") + hipGetErrorString(e));
+            return fail(SG_EHIP);
+        }
+    }
     const HostSetup& hs = c->hs;
     const int m = hs.m, P = hs.P;
     const size_t ncell = (size_t)n * n;
@@ -909,6 +917,24 @@ int sg_qoi(sg_ctx* c, const double* U, double* q, double* J) {
     SG_HIP_CHECK(hipStreamSynchronize(c->stream));
     if (q) std::memcpy(q, c->ws.host_scal, P * sizeof(double));
     *J = c->ws.host_scal[2 * P];
+    return SG_OK;
+}
+
+int sg_qoi_noalloc(sg_ctx* c, const double* U, double* q, double* J) {
+    if (!c || !U || !q || !J || c->hs.disc != SG_DISC_Q1 || !c->qoi_scratch) {
+        set_error("sg_qoi_noalloc: null argument or a discretisation other than SG_DISC_Q1");
+        return SG_EINVAL;
+    }
+    const int P = c->hs.P;
+    if ((size_t)kRedBlocks * P + P > kQoiScratchDoubles) {
+        set_error("sg_qoi_noalloc: P = " + std::to_string(P) + " needs more than the " +
+                  std::to_string(kQoiScratchDoubles) + "-double scratch array");
+        return SG_EINVAL;
+    }
+    // partials in rows of P (every entry written before it is read), adjoint weights after them
+    double* partial = c->qoi_scratch;
+    double* coef = c->qoi_scratch + (size_t)kRedBlocks * P;
+    SG_HIP_CHECK(vec_qoi(c->stream, U, c->ws.wS, c->hs.N, P, partial, q, J, coef));
     return SG_OK;
 }
 

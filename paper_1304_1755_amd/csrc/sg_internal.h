@@ -137,6 +137,7 @@ struct sg_ctx {
     sg_options opt;
     hipStream_t stream = nullptr;
     int device = 0;
+    double* qoi_scratch = nullptr;  // this device's static scratch of sg_qoi_noalloc
     // device data
     double* cell64 = nullptr;   // HostSetup::kcoef on the device
     double* load = nullptr;     // HostSetup::load on the device (SG_DISC_P1)

@@ -41,6 +41,10 @@ hipError_t vec_xpby(hipStream_t s, const double* z, double b, double* p, size_t 
 hipError_t vec_rhs(hipStream_t s, double* F, int N, int P, double h2);
 hipError_t vec_qoi(hipStream_t s, const double* U, const double* wS, int N, int P, double* partial, double* q,
                    double* J, double* coef);
+// the allocation-free QoI: capacity of its per-device scratch array (doubles), and the
+// array's device address on `device` (looked up once per device, that device current)
+constexpr size_t kQoiScratchDoubles = (size_t)kRedBlocks * 256 + 256;
+hipError_t qoi_scratch_address(int device, double** out);
 hipError_t vec_adj_rhs(hipStream_t s, const double* wS, const double* coef, int N, int P, double* g);
 hipError_t vec_grad_cells(hipStream_t s, int nslot, const double* U, const double* L, int n, int P, int m,
                           const uint32_t* toff, const double* tcoef, double* dc);

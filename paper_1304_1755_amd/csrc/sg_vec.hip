@@ -6,6 +6,8 @@
 // a second one-block kernel sums the partials in a fixed order.  No float
 // atomics, so repeated runs are bitwise identical.
 
+#include <mutex>
+
 #include "sg_internal.h"
 #include "sg_vec.h"
 
@@ -501,6 +503,33 @@ hipError_t vec_grad_params(hipStream_t s, const double* dc, const double* kl, co
     const int nn = (n - 1) * (n - 1);
     hipLaunchKernelGGL(k_grad_a0, dim3((nn + 255) / 256), dim3(256), 0, s, dc, n, m, out_a0);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ allocation-free QoI
+// Scratch of sg_qoi_noalloc: the reduction partials (kRedBlocks rows of P
+// modes), then the adjoint weights (P).  A file-scope device array: every GPU
+// the library runs on holds one copy until the process ends.  In host code the
+// array's name is only a stand-in, so its device address is looked up once per
+// device (with that device current) and that pointer is what the kernels get.
+static __device__ __align__(256) double scratch[kQoiScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t qoi_scratch_address(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace sg
