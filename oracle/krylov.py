@@ -93,6 +93,74 @@ def fgmres(A, F, M, restart=30, tol=1e-8, max_it=1000, x0=None):
     return x, info
 
 
+def gmres_left(A, F, M, restart=10, tol=1e-10, max_it=1000):
+    """Left-preconditioned GMRES(restart) on M A x = M F from x = 0.
+
+    The stop test is the relative residual of the preconditioned system,
+    ||M (F - A x)|| / ||M F|| < tol: the running estimate from the Givens
+    rotations inside a cycle, the recomputed value at the end of each cycle.
+    (Reading of Sec. 6's GMRes(10): preconditioning from the left with the
+    tolerance on the preconditioned residual, the convention of the MATLAB
+    environment the section names.)  Returns (x, info), info["true"] holding
+    ||F - A x|| / ||F|| after each cycle.
+    """
+    F = np.asarray(F, dtype=np.float64).ravel()
+    x = np.zeros_like(F)
+    MF = M(F)
+    nMF = np.linalg.norm(MF)
+    nF = np.linalg.norm(F)
+    info = dict(iters=0, restarts=0, est=[], true=[], converged=False)
+    if nMF == 0.0:
+        info["converged"] = True
+        return x, info
+    while info["iters"] < max_it:
+        r = M(F - A(x))
+        beta = np.linalg.norm(r)
+        if beta / nMF < tol:
+            info["converged"] = True
+            break
+        V = [r / beta]
+        H = np.zeros((restart + 1, restart))
+        cs = np.zeros(restart)
+        sn = np.zeros(restart)
+        g = np.zeros(restart + 1)
+        g[0] = beta
+        k = 0
+        for j in range(restart):
+            w = M(A(V[j]))
+            for i in range(j + 1):
+                H[i, j] = np.dot(V[i], w)
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] > 0.0:
+                V.append(w / H[j + 1, j])
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j] = H[j, j] / den
+            sn[j] = H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            info["iters"] += 1
+            info["est"].append(abs(g[j + 1]) / nMF)
+            k = j + 1
+            if abs(g[j + 1]) / nMF < tol or len(V) == j + 1 or info["iters"] >= max_it:
+                break
+        y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
+        for i in range(k):
+            x = x + y[i] * V[i]
+        info["true"].append(np.linalg.norm(F - A(x)) / nF)
+        if np.linalg.norm(M(F - A(x))) / nMF < tol:
+            info["converged"] = True
+            break
+        info["restarts"] += 1
+    return x, info
+
+
 def pcg(A, F, M, tol=1e-8, max_it=1000, x0=None):
     """Preconditioned conjugate gradients with an SPD preconditioner M."""
     F = np.asarray(F, dtype=np.float64).ravel()
