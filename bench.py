@@ -155,7 +155,7 @@ def paper_table3(sgbt, stream):
             row["ms" + tag] = ms
         rows[str(sigma)] = row
     return {"solvers": [name for name, _ in solvers], "rtol": 1e-10, "unknowns": 833490,
-            "smoothers": {"iters": "four-colour V(2,2)", "iters_lex": "lexicographic V(2,2), as in Sec. 6"},
+            "smoothers": {"iters": "four-colour V(2,2)", "iters_lex": "lexicographic V(2,2) (a reading of Sec. 6's point Gauss-Seidel)"},
             "sigma": rows}
 
 

@@ -67,8 +67,9 @@ extern "C" {
 #define SG_COLOUR_FOUR 0 /* colour (I mod 2) + 2 (J mod 2): exact Gauss-Seidel for the 9-point stencil */
 #define SG_COLOUR_RB 1   /* colour (I + J) mod 2, each colour updated from its start-of-colour values */
 #define SG_COLOUR_LEX 2  /* lexicographic point Gauss-Seidel (x fastest), forward before and backward after
-                            the coarse correction: the smoother of Sec. 6.  Sequential fronts: for grids of
-                            the paper's sizes, not for throughput */
+                            the coarse correction: a reading of the point Gauss-Seidel that Sec. 6 names
+                            (the paper gives no ordering).  Sequential fronts: for grids of the paper's
+                            sizes, not for throughput */
 
 /* discretisations (see above) */
 #define SG_DISC_Q1 0

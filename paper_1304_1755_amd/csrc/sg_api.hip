@@ -733,6 +733,14 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
         if ((rc = upload(c, &lv.sten64, hs.mg_sten[l]))) return fail(rc);
         std::vector<float> s32(hs.mg_sten[l].begin(), hs.mg_sten[l].end());
         if ((rc = upload(c, &lv.sten32, s32))) return fail(rc);
+        std::vector<double> rd64((size_t)lv.N);
+        std::vector<float> rd32((size_t)lv.N);
+        for (int i = 0; i < lv.N; ++i) {
+            rd64[i] = 1.0 / hs.mg_sten[l][(size_t)i * 9 + 4];
+            rd32[i] = 1.0f / s32[(size_t)i * 9 + 4];
+        }
+        if ((rc = upload(c, &lv.rdiag64, rd64))) return fail(rc);
+        if ((rc = upload(c, &lv.rdiag32, rd32))) return fail(rc);
     }
     if ((rc = upload_plan(c, make_plan(hs, 0, P, 0, P, true, true, true), c->plan_full))) return fail(rc);
     c->plan_down.assign(hs.p + 1, Plan{});

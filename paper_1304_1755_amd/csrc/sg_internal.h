@@ -100,6 +100,8 @@ struct Level {
     int n, nx, N;          // cells, interior nodes per side, interior nodes
     double* sten64;        // N x 9
     float* sten32;
+    double* rdiag64;       // N reciprocals of the stencil diagonals (the smoothers multiply by them)
+    float* rdiag32;
     // work buffers, capacity N x P
     double* u64; double* f64; double* r64; double* w64;  // w: second smoothing buffer
     float* u32; float* f32; float* r32; float* w32;

@@ -11,7 +11,8 @@
 //
 // Components: multi-colour Gauss-Seidel (four colours (I mod 2, J mod 2), or
 // red/black with each colour updated from its start-of-colour values) or
-// the lexicographic point Gauss-Seidel of Sec. 6 (front by front, one
+// lexicographic point Gauss-Seidel, x fastest (a reading of the point
+// Gauss-Seidel that Sec. 6 names without an ordering; front by front, one
 // workgroup per right-hand side; for grids of the paper's sizes),
 // residual, restriction R = P^T, prolongation P, and the coarsest grid
 // solved with the explicit inverse of its operator in double precision.  P is
@@ -148,8 +149,9 @@ __global__ void k_cast(const Ts* __restrict__ src, int lds, Td* __restrict__ dst
 // those neighbours are skipped and u needs no clearing beforehand.  (For
 // red/black the same-colour diagonal neighbours are also still zero.)
 template <typename T, bool WAVE_NODE>
-__global__ void k_gs(const T* __restrict__ sten, T* __restrict__ u, int ldu, const T* __restrict__ f, int ldf,
-                     T* __restrict__ out, int ldo, int nx, int width, int rb, int q, int nxc, int nyc, int first) {
+__global__ void k_gs(const T* __restrict__ sten, const T* __restrict__ rdiag, T* __restrict__ u, int ldu,
+                     const T* __restrict__ f, int ldf, T* __restrict__ out, int ldo, int nx, int width, int rb, int q,
+                     int nxc, int nyc, int first) {
     const int mode = blockIdx.y * blockDim.x + threadIdx.x;
     int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.y + threadIdx.y;
     if (WAVE_NODE) t = __builtin_amdgcn_readfirstlane(t);  // one node per wavefront: scalar stencil loads
@@ -184,7 +186,7 @@ __global__ void k_gs(const T* __restrict__ sten, T* __restrict__ u, int ldu, con
             acc -= st[(dy + 1) * 3 + (dx + 1)] * u[((size_t)yy * nx + xx) * ldu + mode];
         }
     }
-    const T val = acc / st[4];
+    const T val = acc * rdiag[node];
     if (out)
         out[node * ldo + mode] = val;
     else
@@ -529,7 +531,8 @@ template <typename T>
 constexpr int gs_ring() { return sizeof(T) == 4 ? 4 : 3; }
 
 template <typename T, bool OWNZ, int SEG>
-__global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, const T* __restrict__ A, int lda,
+__global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, const T* __restrict__ rdiag,
+                                                 const T* __restrict__ A, int lda,
                                                  const T* __restrict__ V, int ldv, const T* __restrict__ f, int ldf,
                                                  T* __restrict__ B, int ldb, int nx, int width, int py, int fx,
                                                  int vert_zero, int nseg, int nrows) {
@@ -550,11 +553,12 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     const int x1 = min(x0 + SEG, nx);
     const bool has_dn = y > 0 && !vert_zero, has_up = y + 1 < nx && !vert_zero;
     const int ydn = y > 0 ? y - 1 : y, yup = y + 1 < nx ? y + 1 : y;
-    // stencils of columns x0-1 .. x0+SEG (clamped), column c at stl[c * SP]
-    for (int i = threadIdx.x; i < (SEG + 2) * 9; i += blockDim.x) {
-        const int c = i / 9, e = i - c * 9;
+    // stencils of columns x0-1 .. x0+SEG (clamped), column c at stl[c * SP], the reciprocal
+    // of its diagonal at stl[c * SP + 9]
+    for (int i = threadIdx.x; i < (SEG + 2) * 10; i += blockDim.x) {
+        const int c = i / 10, e = i - c * 10;
         const int x = min(max(x0 - 1 + c, 0), nx - 1);
-        stl[c * SP + e] = sten[((size_t)y * nx + x) * 9 + e];
+        stl[c * SP + e] = e < 9 ? sten[((size_t)y * nx + x) * 9 + e] : rdiag[(size_t)y * nx + x];
     }
     __syncthreads();
     auto cx = [&](int x) { return min(max(x, 0), nx - 1); };
@@ -580,7 +584,7 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
         acc -= st[0] * d0 + st[1] * d1 + st[2] * d2;
         acc -= st[6] * u0 + st[7] * u1 + st[8] * u2;
         acc -= st[3] * wl + st[5] * wr;
-        return acc / st[4];
+        return acc * st[9];
     };
     const int sf = x0 + (fx ? 0 : 1);  // first S node of the segment (S parity is 1 - fx)
     // ring slots: step i reads A(s+2), f(s), f(s+1) and the neighbour rows at s+1, s+2
@@ -648,7 +652,8 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
 // every lane issues all its loads at once.  Addresses are clamped into the
 // grid and values outside it replaced by zero.
 template <typename T, bool OWNZ>
-__global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ sten, const T* __restrict__ A, int lda,
+__global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ sten, const T* __restrict__ rdiag,
+                                                        const T* __restrict__ A, int lda,
                                                         const T* __restrict__ V, int ldv, const T* __restrict__ f,
                                                         int ldf, T* __restrict__ B, int ldb, int nx, int width,
                                                         int wp_log2, int py, int fx, int vert_zero, int npairs,
@@ -669,7 +674,7 @@ __global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ st
     auto gA = [&](int x) -> T { return OWNZ ? T(0) : A[((size_t)y * nx + cx(x)) * lda + mode]; };
     auto gV = [&](int yy, int x) -> T { return V[((size_t)yy * nx + cx(x)) * ldv + mode]; };
     auto gf = [&](int x) -> T { return f[((size_t)y * nx + cx(x)) * ldf + mode]; };
-    T a[3], fv[3], dn[5], up[5], st[3][9];
+    T a[3], fv[3], dn[5], up[5], st[3][9], rd[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         a[i] = gA(s - 2 + 2 * i);
@@ -677,6 +682,7 @@ __global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ st
         const T* sp = sten + ((size_t)y * nx + cx(s - 1 + i)) * 9;
 #pragma unroll
         for (int e = 0; e < 9; ++e) st[i][e] = sp[e];
+        rd[i] = rdiag[(size_t)y * nx + cx(s - 1 + i)];
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -697,7 +703,7 @@ __global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ st
         acc -= c[0] * dn[i] + c[1] * dn[i + 1] + c[2] * dn[i + 2];
         acc -= c[6] * up[i] + c[7] * up[i + 1] + c[8] * up[i + 2];
         acc -= c[3] * wl + c[5] * wr;
-        return acc / c[4];
+        return acc * rd[i];
     };
     const T Fl = inx(s - 1) ? relax(0, a[0], a[1]) : T(0);
     const T Fr = inx(s + 1) ? relax(2, a[1], a[2]) : T(0);
@@ -720,6 +726,7 @@ struct FusedLevels {
     int nx[kMaxFusedLevels];
     int off[kMaxFusedLevels];       // LDS element offset of u_l (f_l follows at off + N_l)
     const T* sten[kMaxFusedLevels];
+    const T* rdiag[kMaxFusedLevels];  // reciprocals of the stencil diagonals
     int roff;                       // LDS element offset of the residual / staging array
     int p1;                         // transfer of the P1 triangulation (else bilinear)
 };
@@ -729,7 +736,7 @@ constexpr int fused_nx_max() { return sizeof(T) == 4 ? 63 : 31; }
 
 // one relaxation of node (x, y) against the current values of its neighbours
 template <typename T, typename G>
-__device__ __forceinline__ T relax_node(const T* __restrict__ s9, T fval, int x, int y, int nx, G get) {
+__device__ __forceinline__ T relax_node(const T* __restrict__ s9, T rd, T fval, int x, int y, int nx, G get) {
     T acc = fval;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
@@ -743,7 +750,7 @@ __device__ __forceinline__ T relax_node(const T* __restrict__ s9, T fval, int x,
             acc -= s9[(dy + 1) * 3 + (dx + 1)] * get(yy * nx + xx);
         }
     }
-    return acc / s9[4];
+    return acc * rd;
 }
 
 // Lexicographic order (x fastest, then y) for a 9-point stencil: the
@@ -758,7 +765,8 @@ __device__ __forceinline__ void lex_front(int d, int nx, int& ylo, int& yhi) {
 
 // mode 0: four colours; 1: red/black from start-of-colour values; 2: lexicographic
 template <typename T>
-__device__ void lds_smooth(const T* __restrict__ st, T* u, const T* f, T* stage, int nx, int mode, bool reverse,
+__device__ void lds_smooth(const T* __restrict__ st, const T* __restrict__ rdiag, T* u, const T* f, T* stage, int nx,
+                           int mode, bool reverse,
                            int nu) {
     if (mode == 2) {
         const int nd = 3 * (nx - 1) + 1;
@@ -769,7 +777,8 @@ __device__ void lds_smooth(const T* __restrict__ st, T* u, const T* f, T* stage,
                 lex_front(d, nx, ylo, yhi);
                 for (int y = ylo + (int)threadIdx.x; y <= yhi; y += blockDim.x) {
                     const int x = d - 2 * y, node = y * nx + x;
-                    u[node] = relax_node<T>(st + (size_t)node * 9, f[node], x, y, nx, [&](int i) { return u[i]; });
+                    u[node] = relax_node<T>(st + (size_t)node * 9, rdiag[node], f[node], x, y, nx,
+                                            [&](int i) { return u[i]; });
                 }
                 __syncthreads();
             }
@@ -803,7 +812,7 @@ __device__ void lds_smooth(const T* __restrict__ st, T* u, const T* f, T* stage,
                         acc -= s9[(dy + 1) * 3 + (dx + 1)] * u[yy * nx + xx];
                     }
                 }
-                const T val = acc / s9[4];
+                const T val = acc * rdiag[node];
                 if (rb) stage[node] = val; else u[node] = val;
             }
             __syncthreads();
@@ -823,7 +832,8 @@ __device__ void lds_smooth(const T* __restrict__ st, T* u, const T* f, T* stage,
 // walks the fronts of lex_front in place, with a workgroup barrier between
 // fronts.  zero_start: the column starts from zero (cleared here).
 template <typename T>
-__global__ void __launch_bounds__(256) k_gs_lex(const T* __restrict__ sten, T* u, int ldu, const T* __restrict__ f,
+__global__ void __launch_bounds__(256) k_gs_lex(const T* __restrict__ sten, const T* __restrict__ rdiag, T* u,
+                                                int ldu, const T* __restrict__ f,
                                                 int ldf, int nx, int reverse, int zero_start) {
     const int col = blockIdx.x;
     if (zero_start) {
@@ -837,7 +847,7 @@ __global__ void __launch_bounds__(256) k_gs_lex(const T* __restrict__ sten, T* u
         lex_front(d, nx, ylo, yhi);
         for (int y = ylo + (int)threadIdx.x; y <= yhi; y += blockDim.x) {
             const int x = d - 2 * y, node = y * nx + x;
-            u[(size_t)node * ldu + col] = relax_node<T>(sten + (size_t)node * 9, f[(size_t)node * ldf + col], x, y,
+            u[(size_t)node * ldu + col] = relax_node<T>(sten + (size_t)node * 9, rdiag[node], f[(size_t)node * ldf + col], x, y,
                                                        nx, [&](int i) { return u[(size_t)i * ldu + col]; });
         }
         __syncthreads();
@@ -865,7 +875,7 @@ __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const d
         T* f = u + N;
         for (int i = threadIdx.x; i < N; i += blockDim.x) u[i] = T(0);
         __syncthreads();
-        lds_smooth<T>(fl.sten[l], u, f, r, nx, mode, false, nu1);
+        lds_smooth<T>(fl.sten[l], fl.rdiag[l], u, f, r, nx, mode, false, nu1);
         // residual r = f - K u
         for (int node = threadIdx.x; node < N; node += blockDim.x) {
             const int y = node / nx, x = node - y * nx;
@@ -917,7 +927,7 @@ __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const d
             u[node] += prolong_value<T>([&](int X, int Y) { return ec[Y * nxc + X]; }, nxc, x, y, fl.p1 != 0);
         }
         __syncthreads();
-        lds_smooth<T>(fl.sten[l], u, f, r, nx, mode, true, nu2);
+        lds_smooth<T>(fl.sten[l], fl.rdiag[l], u, f, r, nx, mode, true, nu2);
     }
     {
         const int N0 = fl.nx[0] * fl.nx[0];
@@ -936,10 +946,12 @@ struct OwnNodes {
     int node[4];
     int x[4], y[4];
     T st[4][9];
+    T rd[4];  // reciprocal of the diagonal
 };
 
 template <typename T>
-__device__ __forceinline__ void own_nodes(const T* __restrict__ sten, int nx, OwnNodes<T>& on) {
+__device__ __forceinline__ void own_nodes(const T* __restrict__ sten, const T* __restrict__ rdiag, int nx,
+                                          OwnNodes<T>& on) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int px = (q & 1) ^ 1, py = (q >> 1) ^ 1;
@@ -953,6 +965,7 @@ __device__ __forceinline__ void own_nodes(const T* __restrict__ sten, int nx, Ow
             on.node[q] = on.y[q] * nx + on.x[q];
 #pragma unroll
             for (int e = 0; e < 9; ++e) on.st[q][e] = sten[(size_t)on.node[q] * 9 + e];
+            on.rd[q] = rdiag[on.node[q]];
         }
     }
 }
@@ -985,7 +998,7 @@ __device__ __forceinline__ void own_smooth(const OwnNodes<T>& on, T* u, const T*
             const int q = reverse ? 3 - qi : qi;
             if (on.node[q] >= 0) {
                 const int nd = on.node[q];
-                u[nd] = stencil_rest<T>(on, q, u, f[nd], nx, true) / on.st[q][4];
+                u[nd] = stencil_rest<T>(on, q, u, f[nd], nx, true) * on.rd[q];
             }
             __syncthreads();
         }
@@ -1039,7 +1052,7 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_fused4(FusedLeve
         const int nx = fl.nx[l], N = nx * nx;
         T* u = lds + fl.off[l];
         T* f = u + N;
-        own_nodes<T>(fl.sten[l], nx, on);
+        own_nodes<T>(fl.sten[l], fl.rdiag[l], nx, on);
         for (int i = threadIdx.x; i < N; i += blockDim.x) u[i] = T(0);
         __syncthreads();
         own_smooth<T>(on, u, f, nx, false, nu1);
@@ -1061,7 +1074,7 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_fused4(FusedLeve
         T* u = lds + fl.off[l];
         const T* f = u + N;
         const T* ec = lds + fl.off[l + 1];
-        own_nodes<T>(fl.sten[l], nx, on);
+        own_nodes<T>(fl.sten[l], fl.rdiag[l], nx, on);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (on.node[q] < 0) continue;
@@ -1091,6 +1104,7 @@ struct LevelPtr<double> {
     static double* f(Level& l) { return l.f64; }
     static double* r(Level& l) { return l.r64; }
     static const double* s(const Level& l) { return l.sten64; }
+    static const double* rd(const Level& l) { return l.rdiag64; }
 };
 template <>
 struct LevelPtr<float> {
@@ -1099,17 +1113,19 @@ struct LevelPtr<float> {
     static float* f(Level& l) { return l.f32; }
     static float* r(Level& l) { return l.r32; }
     static const float* s(const Level& l) { return l.sten32; }
+    static const float* rd(const Level& l) { return l.rdiag32; }
 };
 
 template <typename T>
-void launch_gs(const Tile& tl, dim3 g, hipStream_t st, const T* sten, T* u, int ldu, const T* f, int ldf, T* out,
+void launch_gs(const Tile& tl, dim3 g, hipStream_t st, const T* sten, const T* rdiag, T* u, int ldu, const T* f,
+               int ldf, T* out,
                int ldo, int nx, int width, int rb, int q, int nxc, int nyc, int first) {
     if (tl.tx == 64)
-        hipLaunchKernelGGL((k_gs<T, true>), g, dim3(tl.tx, tl.ty), 0, st, sten, u, ldu, f, ldf, out, ldo, nx, width,
-                           rb, q, nxc, nyc, first);
+        hipLaunchKernelGGL((k_gs<T, true>), g, dim3(tl.tx, tl.ty), 0, st, sten, rdiag, u, ldu, f, ldf, out, ldo, nx,
+                           width, rb, q, nxc, nyc, first);
     else
-        hipLaunchKernelGGL((k_gs<T, false>), g, dim3(tl.tx, tl.ty), 0, st, sten, u, ldu, f, ldf, out, ldo, nx, width,
-                           rb, q, nxc, nyc, first);
+        hipLaunchKernelGGL((k_gs<T, false>), g, dim3(tl.tx, tl.ty), 0, st, sten, rdiag, u, ldu, f, ldf, out, ldo, nx,
+                           width, rb, q, nxc, nyc, first);
 }
 
 template <typename T>
@@ -1118,7 +1134,8 @@ void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, boo
     Level& lv = c->levels[l];
     const int nx = lv.nx;
     if (c->opt.colour_mode == SG_COLOUR_LEX) {
-        hipLaunchKernelGGL(k_gs_lex<T>, dim3(width), dim3(256), 0, c->stream, LevelPtr<T>::s(lv), u, ldu, f, ldf, nx,
+        hipLaunchKernelGGL(k_gs_lex<T>, dim3(width), dim3(256), 0, c->stream, LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv),
+                           u, ldu, f, ldf, nx,
                            reverse ? 1 : 0, first ? 1 : 0);
         return;
     }
@@ -1129,12 +1146,14 @@ void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, boo
         if (!rb) {
             const int px = (q & 1) ^ 1, py = (q >> 1) ^ 1;
             const int nxc = (nx - px + 1) / 2, nyc = (nx - py + 1) / 2;
-            launch_gs<T>(tl, grid2(nxc * nyc, width, tl), c->stream, LevelPtr<T>::s(lv), u, ldu, f, ldf, nullptr, 0,
+            launch_gs<T>(tl, grid2(nxc * nyc, width, tl), c->stream, LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv), u, ldu,
+                         f, ldf, nullptr, 0,
                          nx, width, 0, q, nxc, nyc, first ? 1 : 0);
         } else {
             const int nxc = (nx + 1) / 2, nyc = nx;
             T* stage = LevelPtr<T>::r(lv);  // residual buffer is free during smoothing
-            launch_gs<T>(tl, grid2(nxc * nyc, width, tl), c->stream, LevelPtr<T>::s(lv), u, ldu, f, ldf, stage,
+            launch_gs<T>(tl, grid2(nxc * nyc, width, tl), c->stream, LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv), u, ldu,
+                         f, ldf, stage,
                          width, nx, width, 1, q, nxc, nyc, first ? 1 : 0);
             hipLaunchKernelGGL(k_copy_colour<T>, grid2(nxc * nyc, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
                                (const T*)stage, width, u, ldu, nx, width, q, nxc, nyc);
@@ -1178,7 +1197,7 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
             if (width >= 32) {
                 auto go = [&](auto kern) {
                     hipLaunchKernelGGL(kern, dim3(nrows * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv),
-                                       (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py, fx, vzero, nseg,
+                                       LevelPtr<T>::rd(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py, fx, vzero, nseg,
                                        nrows);
                 };
                 if (own_zero)
@@ -1193,12 +1212,12 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
                 const int nblk = (int)((lanes + 255) / 256);
                 if (own_zero)
                     hipLaunchKernelGGL((k_gs_rows_narrow<T, true>), dim3(nblk), dim3(256), 0, c->stream,
-                                       LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width,
-                                       wl, py, fx, vzero, npairs, nrows);
+                                       LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv), (const T*)src, lds, vsrc, ldv, f, ldf,
+                                       dst, ldd, nx, width, wl, py, fx, vzero, npairs, nrows);
                 else
                     hipLaunchKernelGGL((k_gs_rows_narrow<T, false>), dim3(nblk), dim3(256), 0, c->stream,
-                                       LevelPtr<T>::s(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width,
-                                       wl, py, fx, vzero, npairs, nrows);
+                                       LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv), (const T*)src, lds, vsrc, ldv, f, ldf,
+                                       dst, ldd, nx, width, wl, py, fx, vzero, npairs, nrows);
             }
         }
         std::swap(src, dst);
@@ -1278,6 +1297,7 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             fl.nx[i] = lv.nx;
             fl.off[i] = off;
             fl.sten[i] = LevelPtr<T>::s(lv);
+            fl.rdiag[i] = LevelPtr<T>::rd(lv);
             off += 2 * lv.N;
         }
         fl.roff = off;
