@@ -56,7 +56,7 @@ __device__ __forceinline__ int remap_block_xcd(int b, int nb) {
 }
 
 constexpr int kApplyRows = 2;        // grid rows per workgroup
-constexpr int kMinApplyWaves = 2048;  // below this many wavefronts a launch takes shorter segments
+constexpr int kMinApplyWaves = 16384;  // below this many wavefronts a launch takes shorter segments (narrow coupling plans, small grids)
 
 template <typename F, int... J>
 __device__ __forceinline__ void unroll_steps(F&& f, std::integer_sequence<int, J...>) {
