@@ -72,7 +72,7 @@ __device__ __forceinline__ void unroll_steps(F&& f, std::integer_sequence<int, J
 // small, so several workgroups share a CU and hide memory latency; two rows
 // per workgroup share the window's middle rows and the cell row between them,
 // and halve the synchronizations per node.
-template <int M, int NS, int RW, typename Tin, typename Tout, bool HAS_R, bool TRI>
+template <int M, int NS, int RW, typename Tin, typename Tout, bool HAS_R, bool TRI, int NB>
 __global__ void __launch_bounds__(NS * 64)
 k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int ldr,
            Tout* __restrict__ Y, int ldy, const double* __restrict__ cell,
@@ -100,11 +100,11 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     const bool vin = t < W_in, vout = t < W_out;
     // this lane's partner list (16-bit exchange indices) and the slot's
     // per-position coefficients (uniform) and number of used positions
-    const int npos = __builtin_amdgcn_readfirstlane(npos_slot[s]);
+    (void)npos_slot;  // the launch picks NB >= every slot's ceil(npos / 4)
     const double* cw = xcoef + s * kNPos;
-    uint32_t off[kNPos / 2];
+    uint32_t off[2 * NB];
 #pragma unroll
-    for (int j = 0; j < kNPos / 2; ++j) off[j] = xoff[t * (kNPos / 2) + j];
+    for (int j = 0; j < 2 * NB; ++j) off[j] = xoff[t * (kNPos / 2) + j];
     if (threadIdx.x < RW) S[threadIdx.x * NODE + MM * LANES] = 0.0;  // zero entries
 
     // Circular window wb[row][c] of mode vectors, rows y0-1 .. y0+RW: column
@@ -243,18 +243,17 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
                 if (RW > 1 && y0 + q >= nx) break;  // uniform: the last row pair of an odd grid
                 const double* Bq = S + q * NODE;
                 double acc0 = self ? s0[q] : 0.0, acc1 = 0.0;
-                // blocks of four positions; a block past the slot's last used
-                // position is skipped for the whole wave
+                // NB blocks of four positions, enough for every slot of the
+                // plan; unused positions read the zero entry with coefficient 0
+                // (no per-block branch: the gathers of all blocks issue together)
 #pragma unroll
-                for (int blk = 0; blk < kNPos / 4; ++blk) {
-                    if (blk * 4 < npos) {
-                        const double v0 = Bq[off[2 * blk] & 0xFFFFu], v1 = Bq[off[2 * blk] >> 16];
-                        const double v2 = Bq[off[2 * blk + 1] & 0xFFFFu], v3 = Bq[off[2 * blk + 1] >> 16];
-                        acc0 = fma(cw[4 * blk], v0, acc0);
-                        acc1 = fma(cw[4 * blk + 1], v1, acc1);
-                        acc0 = fma(cw[4 * blk + 2], v2, acc0);
-                        acc1 = fma(cw[4 * blk + 3], v3, acc1);
-                    }
+                for (int blk = 0; blk < NB; ++blk) {
+                    const double v0 = Bq[off[2 * blk] & 0xFFFFu], v1 = Bq[off[2 * blk] >> 16];
+                    const double v2 = Bq[off[2 * blk + 1] & 0xFFFFu], v3 = Bq[off[2 * blk + 1] >> 16];
+                    acc0 = fma(cw[4 * blk], v0, acc0);
+                    acc1 = fma(cw[4 * blk + 1], v1, acc1);
+                    acc0 = fma(cw[4 * blk + 2], v2, acc0);
+                    acc1 = fma(cw[4 * blk + 3], v3, acc1);
                 }
                 const double acc = acc0 + acc1;
                 if (vout) st_from_double(yrow[q] + (size_t)x * ldy + t, HAS_R ? rv[q] - acc : acc);
@@ -277,7 +276,13 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     }
 }
 
-template <typename Tin, typename Tout, int M, int NS, bool TRI>
+// blocks of four partner positions a kernel holds for m KL terms: enough for
+// every slot of the full plan at any p with P <= 256 (at most 8, 12, 14, 12, 13,
+// 11, 10, 11 positions for m = 1..8); coupling plans that need more take 4
+template <int M>
+constexpr int nb_for_m() { return M <= 0 ? 1 : M == 1 ? 2 : (M == 3 || M == 5) ? 4 : 3; }
+
+template <typename Tin, typename Tout, int M, int NS, bool TRI, int NB>
 hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
                     int ldy, const double* cell, int n, const void* zin) {
     constexpr int RW = kApplyRows;
@@ -289,25 +294,35 @@ hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, cons
     const int nseg = (nx + seg - 1) / seg;
     const int blocks = (nx + RW - 1) / RW * nseg;
     if (R)
-        hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, true, TRI>), dim3(blocks), dim3(NS * 64), 0, st,
+        hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, true, TRI, NB>), dim3(blocks), dim3(NS * 64), 0, st,
                            (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_xoff, pl.d_xcoef, pl.d_npos, n, pl.W_in,
                            pl.W_out, pl.self, (const Tin*)zin, seg, nseg);
     else
-        hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, false, TRI>), dim3(blocks), dim3(NS * 64), 0, st,
+        hipLaunchKernelGGL((k_sg_apply<M, NS, RW, Tin, Tout, false, TRI, NB>), dim3(blocks), dim3(NS * 64), 0, st,
                            (const Tin*)U, ldu, R, ldr, (Tout*)Y, ldy, cell, pl.d_xoff, pl.d_xcoef, pl.d_npos, n, pl.W_in,
                            pl.W_out, pl.self, (const Tin*)zin, seg, nseg);
     return hipGetLastError();
 }
 
+template <typename Tin, typename Tout, int M, bool TRI, int NB>
+hipError_t launch_nb(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
+                     int ldy, const double* cell, int n, const void* zin) {
+    switch (pl.nslot) {
+        case 1: return launch_t<Tin, Tout, M, 1, TRI, NB>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 2: return launch_t<Tin, Tout, M, 2, TRI, NB>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 3: return launch_t<Tin, Tout, M, 3, TRI, NB>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+        case 4: return launch_t<Tin, Tout, M, 4, TRI, NB>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename Tin, typename Tout, int M, bool TRI>
 hipError_t launch_ns(hipStream_t st, const Plan& pl, const void* U, int ldu, const double* R, int ldr, void* Y,
                      int ldy, const double* cell, int n, const void* zin) {
-    switch (pl.nslot) {
-        case 1: return launch_t<Tin, Tout, M, 1, TRI>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 2: return launch_t<Tin, Tout, M, 2, TRI>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 3: return launch_t<Tin, Tout, M, 3, TRI>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-        case 4: return launch_t<Tin, Tout, M, 4, TRI>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
-    }
+    constexpr int NB = nb_for_m<M>();
+    if (pl.nblk_max <= NB) return launch_nb<Tin, Tout, M, TRI, NB>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
+    if constexpr (NB < kNPos / 4)
+        return launch_nb<Tin, Tout, M, TRI, kNPos / 4>(st, pl, U, ldu, R, ldr, Y, ldy, cell, n, zin);
     return hipErrorInvalidValue;
 }
 
