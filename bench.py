@@ -166,8 +166,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3")
     ap.add_argument("--burst", type=int, default=12, help="double applies timed per step")
-    ap.add_argument("--mode", default="full", choices=["full", "apply", "paper"],
+    ap.add_argument("--mode", default="full", choices=["full", "apply", "vcycle", "paper"],
                     help="apply: only the double apply loop (for profiler counter runs); "
+                         "vcycle: only V(2,2) cycles on 126- and 56-mode blocks, float and double "
+                         "(the two widest degree levels of the workload; for profiler counter runs); "
                          "paper: only the Sec. 6 Table 3 solvers")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-paper", action="store_true", help="skip the Sec. 6 iteration-count table")
@@ -217,6 +219,26 @@ def main():
         dt = (time.perf_counter() - t0) / args.steps
         print(json.dumps({"mode": "apply", "ms_per_apply_wall": dt * 1e3, "bytes": nbytes,
                           "copy_bytes": 16 * N * P}))
+        return
+
+    if args.mode == "vcycle":
+        a = torch.empty(N * P, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)  # the same calibration copy as --mode apply
+        out = {"mode": "vcycle", "copy_bytes": 16 * N * P}
+        for W in (126, 56):
+            for prec, dt in ((sgbt.SG_F32, torch.float32), (sgbt.SG_F64, torch.float64)):
+                f = (torch.rand((N, W), dtype=torch.float64, device="cuda", generator=gen) * 2 - 1).to(dt)
+                u = torch.empty_like(f)
+                for _ in range(args.warmup):
+                    prob.vcycle(f, u, prec)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    prob.vcycle(f, u, prec)
+                torch.cuda.synchronize()
+                out[f"ms_W{W}_{'f32' if prec == sgbt.SG_F32 else 'f64'}"] = (time.perf_counter() - t0) / args.steps * 1e3
+        print(json.dumps(out))
         return
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.burst)]
