@@ -741,6 +741,28 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
         }
         if ((rc = upload(c, &lv.rdiag64, rd64))) return fail(rc);
         if ((rc = upload(c, &lv.rdiag32, rd32))) return fail(rc);
+        if (lv.nx <= kLdsCycleMaxNx) {
+            // colour q = (x odd when q is even) + (y odd when q < 2), the order of a forward sweep
+            std::vector<double> c64;
+            std::vector<float> c32;
+            for (int q = 0; q < 4; ++q) {
+                const int px = (q & 1) ^ 1, py = (q >> 1) ^ 1;
+                for (int y = py; y < lv.nx; y += 2)
+                    for (int x = px; x < lv.nx; x += 2) {
+                        const size_t node = (size_t)y * lv.nx + x;
+                        for (int e = 0; e < 9; ++e) {
+                            c64.push_back(hs.mg_sten[l][node * 9 + e]);
+                            c32.push_back(s32[node * 9 + e]);
+                        }
+                        c64.push_back(rd64[node]);
+                        c32.push_back(rd32[node]);
+                        c32.push_back(0.0f);
+                        c32.push_back(0.0f);
+                    }
+            }
+            if ((rc = upload(c, &lv.cst64, c64))) return fail(rc);
+            if ((rc = upload(c, &lv.cst32, c32))) return fail(rc);
+        }
     }
     if ((rc = upload_plan(c, make_plan(hs, 0, P, 0, P, true, true, true), c->plan_full))) return fail(rc);
     c->plan_down.assign(hs.p + 1, Plan{});

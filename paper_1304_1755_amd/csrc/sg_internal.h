@@ -14,6 +14,7 @@ namespace sg {
 constexpr int kMaxM = 8;
 constexpr int kMaxSlots = 4;  // modes per node handled by one wave: up to 4 x 64 = 256
 constexpr int kMaxRestart = 64;
+constexpr int kLdsCycleMaxNx = 63;  // largest grid (interior nodes per side) the fused coarse cycle takes
 
 void set_error(const std::string& msg);
 
@@ -102,6 +103,11 @@ struct Level {
     float* sten32;
     double* rdiag64;       // N reciprocals of the stencil diagonals (the smoothers multiply by them)
     float* rdiag32;
+    // grids the fused coarse cycle keeps in LDS: the stencils in colour order (colours in sweep
+    // order, nodes of a colour y-major), 9 coefficients and the reciprocal diagonal per node,
+    // padded to 10 doubles / 12 floats so that a thread loads its node's entry in 16-byte pieces
+    double* cst64;
+    float* cst32;
     // work buffers, capacity N x P
     double* u64; double* f64; double* r64; double* w64;  // w: second smoothing buffer
     float* u32; float* f32; float* r32; float* w32;

@@ -1091,6 +1091,227 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_fused4(FusedLeve
     }
 }
 
+// Padded form of the fused four-colour coarse cycle, for grids of 2^k - 1
+// interior nodes per side (63, 31, 15, 7, 3 above the coarsest).  Every
+// level's u sits in LDS inside a border of zeros, (nx + 2)^2 values, so a
+// relaxation reads its eight neighbours without bounds tests; the level sizes
+// are compile-time constants (one code path per size), so the neighbour
+// offsets are immediates of the LDS loads.  A thread's stencils come from the
+// level's colour-ordered copy in 16-byte pieces.  The arithmetic of every
+// relaxation, residual, restriction and prolongation is that of
+// k_vcycle_fused4 (the border's zeros enter as exact zero terms).
+template <typename T>
+struct PadLevels {
+    int nlev;                       // fused levels, the last is the coarsest
+    int nx[kMaxFusedLevels];
+    int uoff[kMaxFusedLevels];      // LDS element offset of the padded u_l
+    int foff[kMaxFusedLevels];      // LDS element offset of f_l (nx^2 values)
+    const T* cst[kMaxFusedLevels];  // colour-ordered stencils of the levels above the coarsest
+    int roff;                       // LDS element offset of the residual of the top level
+    int p1;                         // transfer of the P1 triangulation (else bilinear)
+};
+
+template <typename T>
+constexpr int cst_pitch() { return sizeof(T) == 4 ? 12 : 10; }
+
+template <typename T>
+struct OwnPad {
+    T st[4][9];
+    T rd[4];
+};
+
+// the node of colour q owned by thread t on an NX x NX grid
+template <int NX>
+__device__ __forceinline__ bool pad_own(int q, int t, int& x, int& y) {
+    const int px = (q & 1) ^ 1, py = (q >> 1) ^ 1;
+    const int nxc = (NX - px + 1) / 2, nyc = (NX - py + 1) / 2;
+    const int j = t / nxc, i = t - j * nxc;
+    x = px + 2 * i;
+    y = py + 2 * j;
+    return t < nxc * nyc;
+}
+
+// entries of the colours before q in the colour-ordered stencil array
+template <int NX>
+__device__ __forceinline__ int pad_colour_base(int q) {
+    int b = 0;
+    for (int c = 0; c < q; ++c) b += ((NX - ((c & 1) ^ 1) + 1) / 2) * ((NX - ((c >> 1) ^ 1) + 1) / 2);
+    return b;
+}
+
+template <typename T, int NX>
+__device__ __forceinline__ void pad_load_own(const T* __restrict__ cst, OwnPad<T>& on, int tid) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int x, y;
+        if (!pad_own<NX>(q, tid, x, y)) continue;
+        const T* e = cst + (size_t)(pad_colour_base<NX>(q) + tid) * cst_pitch<T>();
+        if constexpr (sizeof(T) == 4) {
+            const float4 a = ((const float4*)e)[0], b = ((const float4*)e)[1], c = ((const float4*)e)[2];
+            on.st[q][0] = a.x; on.st[q][1] = a.y; on.st[q][2] = a.z; on.st[q][3] = a.w;
+            on.st[q][4] = b.x; on.st[q][5] = b.y; on.st[q][6] = b.z; on.st[q][7] = b.w;
+            on.st[q][8] = c.x; on.rd[q] = c.y;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const double2 v = ((const double2*)e)[k];
+                if (2 * k < 9) on.st[q][2 * k] = v.x;
+                if (2 * k + 1 < 9) on.st[q][2 * k + 1] = v.y; else on.rd[q] = v.y;
+            }
+        }
+    }
+}
+
+// f - (K u) at (x, y) on the padded grid, the centre left out when skip_c;
+// the same terms in the same order as stencil_rest, plus exact zeros
+template <typename T, int NX>
+__device__ __forceinline__ T pad_rest(const T (&s9)[9], const T* u, int x, int y, T fval, bool skip_c) {
+    constexpr int PW = NX + 2;
+    const T* c = u + (y + 1) * PW + (x + 1);
+    T acc = fval;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (skip_c && dx == 0 && dy == 0) continue;
+            acc -= s9[(dy + 1) * 3 + (dx + 1)] * c[dy * PW + dx];
+        }
+    return acc;
+}
+
+template <typename T, int NX>
+__device__ __forceinline__ void pad_smooth(const OwnPad<T>& on, T* u, const T* f, bool reverse, int nu, int tid) {
+    constexpr int PW = NX + 2;
+    for (int sweep = 0; sweep < nu; ++sweep)
+#pragma unroll
+        for (int qi = 0; qi < 4; ++qi) {
+            const int q = reverse ? 3 - qi : qi;
+            int x, y;
+            if (pad_own<NX>(q, tid, x, y))
+                u[(y + 1) * PW + x + 1] = pad_rest<T, NX>(on.st[q], u, x, y, f[y * NX + x], true) * on.rd[q];
+            __syncthreads();
+        }
+}
+
+// calls f(integral_constant<int, nx>) for the level sizes of the padded cycle
+template <typename F>
+__device__ __forceinline__ void with_pad_nx(int nx, F&& f) {
+    switch (nx) {
+        case 63: f(std::integral_constant<int, 63>{}); break;
+        case 31: f(std::integral_constant<int, 31>{}); break;
+        case 15: f(std::integral_constant<int, 15>{}); break;
+        case 7: f(std::integral_constant<int, 7>{}); break;
+        case 3: f(std::integral_constant<int, 3>{}); break;
+        default: break;  // the host launches this kernel only for these sizes
+    }
+}
+
+__host__ __device__ constexpr bool pad_cycle_size(int nx) { return nx == 63 || nx == 31 || nx == 15 || nx == 7 || nx == 3; }
+
+template <typename T>
+__global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_pad(PadLevels<T> pl, const double* __restrict__ kinv,
+                                                                    const T* __restrict__ fin, int ldf,
+                                                                    T* __restrict__ uout, int ldu, int nu1, int nu2) {
+    extern __shared__ char smem_raw[];
+    T* lds = (T*)smem_raw;
+    const int col = blockIdx.x;
+    const int L = pl.nlev - 1;
+    const int nx0 = pl.nx[0], N0 = nx0 * nx0;
+    // zero every padded u: the border stays zero, the interiors are the zero initial guesses
+    for (int l = 0; l <= L; ++l) {
+        const int pw = pl.nx[l] + 2;
+        T* u = lds + pl.uoff[l];
+        for (int i = threadIdx.x; i < pw * pw; i += blockDim.x) u[i] = T(0);
+    }
+    {
+        T* f0 = lds + pl.foff[0];
+        for (int i = threadIdx.x; i < N0; i += blockDim.x) f0[i] = fin[(size_t)i * ldf + col];
+    }
+    __syncthreads();
+    T* r = lds + pl.roff;
+    OwnPad<T> on;
+    for (int l = 0; l < L; ++l) {
+        with_pad_nx(pl.nx[l], [&](auto knx) __attribute__((always_inline)) {
+            constexpr int NX = decltype(knx)::value;
+            constexpr int NXC = (NX - 1) / 2;
+            // an opaque copy of the thread index keeps each level's per-thread
+            // addresses inside its visit (hoisted for every level size they
+            // would not fit in registers)
+            int tid = threadIdx.x;
+            __asm__ volatile("" : "+v"(tid));
+            T* u = lds + pl.uoff[l];
+            const T* f = lds + pl.foff[l];
+            pad_load_own<T, NX>(pl.cst[l], on, tid);
+            pad_smooth<T, NX>(on, u, f, false, nu1, tid);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int x, y;
+                if (pad_own<NX>(q, tid, x, y)) r[y * NX + x] = pad_rest<T, NX>(on.st[q], u, x, y, f[y * NX + x], false);
+            }
+            __syncthreads();
+            T* fc = lds + pl.foff[l + 1];
+            for (int node = tid; node < NXC * NXC; node += blockDim.x) {
+                const int Y = node / NXC, X = node - Y * NXC;
+                fc[node] = restrict_value<T>([&](int xx, int yy) { return r[yy * NX + xx]; }, X, Y, pl.p1 != 0);
+            }
+            __syncthreads();
+        });
+    }
+    {
+        // coarsest grid: u = K^{-1} f in double (as coarsest_solve), written into the padded layout
+        const int nxL = pl.nx[L], N = nxL * nxL;
+        const T* f = lds + pl.foff[L];
+        T* u = lds + pl.uoff[L];
+        int G = 1;
+        while (G < 64 && 2 * G * N <= (int)blockDim.x) G *= 2;
+        const int rows = (int)blockDim.x / G;
+        const int g = threadIdx.x % G;
+        for (int i0 = 0; i0 < N; i0 += rows) {  // uniform trip count
+            const int i = i0 + (int)threadIdx.x / G;
+            double acc = 0.0;
+            if (i < N) {
+                const double* row = kinv + (size_t)i * N;
+                for (int j = g; j < N; j += G) acc = fma(row[j], (double)f[j], acc);
+            }
+            for (int o = G / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);  // groups lie inside a wavefront
+            if (i < N && g == 0) {
+                const int y = i / nxL, x = i - y * nxL;
+                u[(y + 1) * (nxL + 2) + x + 1] = (T)acc;
+            }
+        }
+        __syncthreads();
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        with_pad_nx(pl.nx[l], [&](auto knx) __attribute__((always_inline)) {
+            constexpr int NX = decltype(knx)::value;
+            constexpr int PW = NX + 2;
+            constexpr int NXC = (NX - 1) / 2;
+            int tid = threadIdx.x;
+            __asm__ volatile("" : "+v"(tid));
+            T* u = lds + pl.uoff[l];
+            const T* f = lds + pl.foff[l];
+            const T* ec = lds + pl.uoff[l + 1];
+            pad_load_own<T, NX>(pl.cst[l], on, tid);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int x, y;
+                if (pad_own<NX>(q, tid, x, y))
+                    u[(y + 1) * PW + x + 1] += prolong_value<T>(
+                        [&](int X, int Y) { return ec[(Y + 1) * (NXC + 2) + X + 1]; }, NXC, x, y, pl.p1 != 0);
+            }
+            __syncthreads();
+            pad_smooth<T, NX>(on, u, f, true, nu2, tid);
+        });
+    }
+    {
+        const T* u0 = lds + pl.uoff[0];
+        for (int i = threadIdx.x; i < N0; i += blockDim.x) {
+            const int y = i / nx0, x = i - y * nx0;
+            uout[(size_t)i * ldu + col] = u0[(y + 1) * (nx0 + 2) + x + 1];
+        }
+    }
+}
+
 inline dim3 grid2(int rows, int width, const Tile& tl) {
     return dim3((rows + tl.ty - 1) / tl.ty, (width + tl.tx - 1) / tl.tx);
 }
@@ -1105,6 +1326,7 @@ struct LevelPtr<double> {
     static double* r(Level& l) { return l.r64; }
     static const double* s(const Level& l) { return l.sten64; }
     static const double* rd(const Level& l) { return l.rdiag64; }
+    static const double* cst(const Level& l) { return l.cst64; }
 };
 template <>
 struct LevelPtr<float> {
@@ -1114,6 +1336,7 @@ struct LevelPtr<float> {
     static float* r(Level& l) { return l.r32; }
     static const float* s(const Level& l) { return l.sten32; }
     static const float* rd(const Level& l) { return l.rdiag32; }
+    static const float* cst(const Level& l) { return l.cst32; }
 };
 
 template <typename T>
@@ -1284,7 +1507,28 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
                                (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width, (int)p1);
         }
     }
-    if (Lc >= 0) {
+    bool pad = Lc >= 0 && c->opt.colour_mode == SG_COLOUR_FOUR && L - Lc + 1 <= kMaxFusedLevels;
+    for (int l = Lc; pad && l < L; ++l)
+        pad = pad_cycle_size(c->levels[l].nx) && LevelPtr<T>::cst(c->levels[l]) != nullptr;
+    if (pad) {
+        PadLevels<T> pl{};
+        pl.nlev = L - Lc + 1;
+        pl.p1 = p1;
+        int off = 0;
+        for (int i = 0; i < pl.nlev; ++i) {
+            const Level& lv = c->levels[Lc + i];
+            pl.nx[i] = lv.nx;
+            pl.uoff[i] = off;
+            off += (lv.nx + 2) * (lv.nx + 2);
+            pl.foff[i] = off;
+            off += lv.N;
+            pl.cst[i] = LevelPtr<T>::cst(lv);
+        }
+        pl.roff = off;
+        off += c->levels[Lc].N;
+        hipLaunchKernelGGL(k_vcycle_pad<T>, dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T), c->stream,
+                           pl, (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2);
+    } else if (Lc >= 0) {
         FusedLevels<T> fl{};
         fl.nlev = L - Lc + 1;
         if (fl.nlev > kMaxFusedLevels) {
