@@ -86,13 +86,13 @@ int ensure_mg(sg_ctx* c, int is_float) {
         if (is_float && !lv.r32) {
             rc = dalloc(c, &lv.r32, cap);
             if (!rc) rc = dalloc(c, &lv.w32, cap);
-            if (!rc && l > 0) rc = dalloc(c, &lv.u32, cap);
+            if (!rc) rc = dalloc(c, &lv.u32, cap);  // level 0: the cycle's compact iterate
             if (!rc && l > 0) rc = dalloc(c, &lv.f32, cap);
         }
         if (!is_float && !lv.r64) {
             rc = dalloc(c, &lv.r64, cap);
             if (!rc) rc = dalloc(c, &lv.w64, cap);
-            if (!rc && l > 0) rc = dalloc(c, &lv.u64, cap);
+            if (!rc) rc = dalloc(c, &lv.u64, cap);
             if (!rc && l > 0) rc = dalloc(c, &lv.f64, cap);
         }
         if (rc) return rc;

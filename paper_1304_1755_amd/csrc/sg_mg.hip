@@ -1390,11 +1390,16 @@ void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, boo
 constexpr int kMinWalkWaves = 2048;
 
 // nu four-colour sweeps by row phases with ping-pong between u and the
-// level's second buffer; returns with the result in u.  zero_start: u holds
-// the zero initial guess (not read).
+// level's second buffer; returns with the result in uout (u when null; the
+// last sweep writes uout directly when it is a third buffer).  zero_start:
+// u holds the zero initial guess (not read).
 template <typename T>
 void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, bool reverse, int nu,
-                bool zero_start) {
+                bool zero_start, T* uout = nullptr, int lduo = 0) {
+    if (!uout) {
+        uout = u;
+        lduo = ldu;
+    }
     Level& lv = c->levels[l];
     const int nx = lv.nx;
     T* alt = LevelPtr<T>::u2(lv);
@@ -1409,6 +1414,10 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
     int ldd = lda_alt;
     for (int sw = 0; sw < nu; ++sw) {
         const bool own_zero = zero_start && sw == 0;
+        if (sw == nu - 1 && uout != u && uout != src) {
+            dst = uout;
+            ldd = lduo;
+        }
         // forward: rows y odd (fx = 1), then y even (fx = 1); backward: y even (fx = 0), then y odd (fx = 0)
         const int py1 = reverse ? 0 : 1, fx = reverse ? 0 : 1;
         for (int ph = 0; ph < 2; ++ph) {
@@ -1446,11 +1455,11 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
         std::swap(src, dst);
         std::swap(lds, ldd);
     }
-    if (src != u) {
-        // odd number of sweeps: the result is in the second buffer
+    if (src != uout) {
+        // the result is in another buffer (an odd number of sweeps, or none)
         const Tile tl = tile_for(width);
         hipLaunchKernelGGL((k_cast<T, T>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream, (const T*)src,
-                           lds, u, ldu, lv.N, width);
+                           lds, uout, lduo, lv.N, width);
     }
 }
 
@@ -1470,10 +1479,17 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     for (int l = 0; l <= L; ++l)
         if (c->levels[l].nx <= fused_nx_max<T>()) { Lc = l; break; }
     const int Ltop = Lc >= 0 ? Lc : L;  // levels above Ltop are cycled by separate launches
+    // with row sweeps the finest level iterates in its own compact block (row
+    // stride = width) and only the last post-smoothing sweep writes u0, whose
+    // rows may be strided (a slice of a wider block): the stencil reads of the
+    // cycle then touch W contiguous values per node, not one per cache line
+    const bool compact0 = use_row_sweeps<T>(c, width) && Ltop > 0;
+    T* const uc0 = compact0 ? LevelPtr<T>::u(c->levels[0]) : u0;
+    const int ldc0 = compact0 ? width : ldu0;
     auto fptr = [&](int l) -> const T* { return l == 0 ? f0 : LevelPtr<T>::f(c->levels[l]); };
     auto fld = [&](int l) { return l == 0 ? ldf0 : width; };
-    auto uptr = [&](int l) -> T* { return l == 0 ? u0 : LevelPtr<T>::u(c->levels[l]); };
-    auto uld = [&](int l) { return l == 0 ? ldu0 : width; };
+    auto uptr = [&](int l) -> T* { return l == 0 ? uc0 : LevelPtr<T>::u(c->levels[l]); };
+    auto uld = [&](int l) { return l == 0 ? ldc0 : width; };
     for (int l = 0; l < Ltop; ++l) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
@@ -1580,7 +1596,8 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             hipLaunchKernelGGL((k_prolong_add<T, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
                                (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width, (int)p1);
         if (use_row_sweeps<T>(c, width))
-            row_sweeps<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, c->opt.nu2, false);
+            row_sweeps<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, c->opt.nu2, false, l == 0 ? u0 : nullptr,
+                          l == 0 ? ldu0 : 0);
         else
             for (int s = 0; s < c->opt.nu2; ++s) smooth<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, tl, false);
     }
