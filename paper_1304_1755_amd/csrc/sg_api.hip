@@ -300,11 +300,16 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
         return SG_ENAN;
     }
     if (!o.use_x0 && (rc = launch_fill(c->stream, X, 0, 1, (int)np, 1))) return rc;
-    // r = F - A X, kept unnormalized as the first candidate V_0
-    if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
-    SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
-    if ((rc = fetch(c, scal, 1))) return rc;
-    double beta = std::sqrt(hs[0]);
+    // r = F - A X, kept unnormalized as the first candidate V_0 (r = F when X starts at zero)
+    double beta = nF;
+    if (o.use_x0) {
+        if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+        SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
+        if ((rc = fetch(c, scal, 1))) return rc;
+        beta = std::sqrt(hs[0]);
+    } else {
+        SG_HIP_CHECK(hipMemcpyAsync(Vj(0), F, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
     info.rel_res_true = beta / nF;
     if (!std::isfinite(beta)) {
         set_error("initial residual is not finite");

@@ -7,8 +7,10 @@
 // atomics, so repeated runs are bitwise identical.
 
 #include <mutex>
+#include <type_traits>
 
 #include "sg_internal.h"
+
 #include "sg_vec.h"
 
 namespace sg {
@@ -179,10 +181,54 @@ __global__ void k_scale(const double* __restrict__ src, double a, double* __rest
         dst[e] = a * src[e];
 }
 
-// x += sum_i y[i] Z_i  (Z float or double)
+// x += sum_i y[i] Z_i  (Z float or double).  A thread owns pairs of
+// consecutive entries and reads the Z_i four vectors at a time, all loads of a
+// group issued before its multiply-adds; the sum runs over i in order, as a
+// plain loop would.
 template <typename TZ>
-__global__ void k_combine(const TZ* __restrict__ Z, size_t stride, int nz, const double* __restrict__ y,
-                          double* __restrict__ x, size_t len) {
+__global__ void __launch_bounds__(256) k_combine(const TZ* __restrict__ Z, size_t stride, int nz,
+                                                 const double* __restrict__ y, double* __restrict__ x, size_t len) {
+    using TZ2 = typename std::conditional<sizeof(TZ) == 4, float2, double2>::type;
+    __shared__ double ys[kMaxRestart];
+    for (int i = threadIdx.x; i < nz; i += blockDim.x) ys[i] = y[i];
+    __syncthreads();
+    const size_t npair = len / 2;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < npair; e += (size_t)gridDim.x * blockDim.x) {
+        const double2 x0 = ((const double2*)x)[e];
+        double a0 = x0.x, a1 = x0.y;
+        int i = 0;
+        for (; i + 4 <= nz; i += 4) {
+            TZ2 v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = ((const TZ2*)(Z + (size_t)(i + q) * stride))[e];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a0 = fma(ys[i + q], (double)v[q].x, a0);
+                a1 = fma(ys[i + q], (double)v[q].y, a1);
+            }
+        }
+        for (; i < nz; ++i) {
+            const TZ2 v = ((const TZ2*)(Z + (size_t)i * stride))[e];
+            a0 = fma(ys[i], (double)v.x, a0);
+            a1 = fma(ys[i], (double)v.y, a1);
+        }
+        ((double2*)x)[e] = make_double2(a0, a1);
+    }
+    if (len & 1) {  // the last entry of an odd length
+        const size_t e = len - 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            double acc = x[e];
+            for (int i = 0; i < nz; ++i) acc = fma(ys[i], (double)Z[(size_t)i * stride + e], acc);
+            x[e] = acc;
+        }
+    }
+}
+
+// the same sum one entry per thread, for an x that is not 16-byte aligned
+template <typename TZ>
+__global__ void __launch_bounds__(256) k_combine_scalar(const TZ* __restrict__ Z, size_t stride, int nz,
+                                                        const double* __restrict__ y, double* __restrict__ x,
+                                                        size_t len) {
     __shared__ double ys[kMaxRestart];
     for (int i = threadIdx.x; i < nz; i += blockDim.x) ys[i] = y[i];
     __syncthreads();
@@ -436,11 +482,23 @@ hipError_t vec_scale(hipStream_t s, const double* src, double a, double* dst, si
 
 hipError_t vec_combine(hipStream_t s, const void* Z, int z_float, size_t stride, int nz, const double* y, double* x,
                        size_t len) {
-    if (z_float)
-        hipLaunchKernelGGL(k_combine<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)Z, stride, nz, y, x, len);
-    else
-        hipLaunchKernelGGL(k_combine<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)Z, stride, nz, y, x,
-                           len);
+    // pairs of entries need x 16-byte aligned and Z_i starting on an even entry (an even stride)
+    const bool pairs = ((uintptr_t)x % 16 == 0) && ((uintptr_t)Z % 16 == 0) && stride % 2 == 0;
+    if (z_float) {
+        if (pairs)
+            hipLaunchKernelGGL(k_combine<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)Z, stride, nz, y, x,
+                               len);
+        else
+            hipLaunchKernelGGL(k_combine_scalar<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)Z, stride, nz,
+                               y, x, len);
+    } else {
+        if (pairs)
+            hipLaunchKernelGGL(k_combine<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)Z, stride, nz, y,
+                               x, len);
+        else
+            hipLaunchKernelGGL(k_combine_scalar<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)Z, stride,
+                               nz, y, x, len);
+    }
     return hipGetLastError();
 }
 
