@@ -746,6 +746,20 @@ int sg_setup(const sg_options* opt, const double* a0_nodal, const double* kl_amp
         }
         if ((rc = upload(c, &lv.rdiag64, rd64))) return fail(rc);
         if ((rc = upload(c, &lv.rdiag32, rd32))) return fail(rc);
+        {
+            std::vector<double> p64((size_t)lv.N * 10, 0.0);
+            std::vector<float> p32((size_t)lv.N * 12, 0.0f);
+            for (size_t node = 0; node < (size_t)lv.N; ++node) {
+                for (int e = 0; e < 9; ++e) {
+                    p64[node * 10 + e] = hs.mg_sten[l][node * 9 + e];
+                    p32[node * 12 + e] = s32[node * 9 + e];
+                }
+                p64[node * 10 + 9] = rd64[node];
+                p32[node * 12 + 9] = rd32[node];
+            }
+            if ((rc = upload(c, &lv.stp64, p64))) return fail(rc);
+            if ((rc = upload(c, &lv.stp32, p32))) return fail(rc);
+        }
         if (lv.nx <= kLdsCycleMaxNx) {
             // colour q = (x odd when q is even) + (y odd when q < 2), the order of a forward sweep
             std::vector<double> c64;

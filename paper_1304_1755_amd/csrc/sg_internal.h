@@ -108,6 +108,10 @@ struct Level {
     // padded to 10 doubles / 12 floats so that a thread loads its node's entry in 16-byte pieces
     double* cst64;
     float* cst32;
+    // the stencils node by node with the reciprocal diagonal, padded to 10 doubles / 12 floats
+    // (16-byte pieces) for the narrow row smoother
+    double* stp64;
+    float* stp32;
     // work buffers, capacity N x P
     double* u64; double* f64; double* r64; double* w64;  // w: second smoothing buffer
     float* u32; float* f32; float* r32; float* w32;

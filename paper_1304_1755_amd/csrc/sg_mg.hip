@@ -652,7 +652,7 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
 // every lane issues all its loads at once.  Addresses are clamped into the
 // grid and values outside it replaced by zero.
 template <typename T, bool OWNZ>
-__global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ sten, const T* __restrict__ rdiag,
+__global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ stp,
                                                         const T* __restrict__ A, int lda,
                                                         const T* __restrict__ V, int ldv, const T* __restrict__ f,
                                                         int ldf, T* __restrict__ B, int ldb, int nx, int width,
@@ -679,10 +679,21 @@ __global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ st
     for (int i = 0; i < 3; ++i) {
         a[i] = gA(s - 2 + 2 * i);
         fv[i] = gf(s - 1 + i);
-        const T* sp = sten + ((size_t)y * nx + cx(s - 1 + i)) * 9;
+        // the node's padded stencil entry in 16-byte pieces
+        const T* sp = stp + ((size_t)y * nx + cx(s - 1 + i)) * (sizeof(T) == 4 ? 12 : 10);
+        if constexpr (sizeof(T) == 4) {
+            const float4 p0 = ((const float4*)sp)[0], p1 = ((const float4*)sp)[1], p2 = ((const float4*)sp)[2];
+            st[i][0] = p0.x; st[i][1] = p0.y; st[i][2] = p0.z; st[i][3] = p0.w;
+            st[i][4] = p1.x; st[i][5] = p1.y; st[i][6] = p1.z; st[i][7] = p1.w;
+            st[i][8] = p2.x; rd[i] = p2.y;
+        } else {
 #pragma unroll
-        for (int e = 0; e < 9; ++e) st[i][e] = sp[e];
-        rd[i] = rdiag[(size_t)y * nx + cx(s - 1 + i)];
+            for (int k = 0; k < 5; ++k) {
+                const double2 v = ((const double2*)sp)[k];
+                st[i][2 * k] = v.x;
+                if (k < 4) st[i][2 * k + 1] = v.y; else rd[i] = v.y;
+            }
+        }
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -1327,6 +1338,7 @@ struct LevelPtr<double> {
     static const double* s(const Level& l) { return l.sten64; }
     static const double* rd(const Level& l) { return l.rdiag64; }
     static const double* cst(const Level& l) { return l.cst64; }
+    static const double* stp(const Level& l) { return l.stp64; }
 };
 template <>
 struct LevelPtr<float> {
@@ -1337,6 +1349,7 @@ struct LevelPtr<float> {
     static const float* s(const Level& l) { return l.sten32; }
     static const float* rd(const Level& l) { return l.rdiag32; }
     static const float* cst(const Level& l) { return l.cst32; }
+    static const float* stp(const Level& l) { return l.stp32; }
 };
 
 template <typename T>
@@ -1444,11 +1457,11 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
                 const int nblk = (int)((lanes + 255) / 256);
                 if (own_zero)
                     hipLaunchKernelGGL((k_gs_rows_narrow<T, true>), dim3(nblk), dim3(256), 0, c->stream,
-                                       LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv), (const T*)src, lds, vsrc, ldv, f, ldf,
+                                       LevelPtr<T>::stp(lv), (const T*)src, lds, vsrc, ldv, f, ldf,
                                        dst, ldd, nx, width, wl, py, fx, vzero, npairs, nrows);
                 else
                     hipLaunchKernelGGL((k_gs_rows_narrow<T, false>), dim3(nblk), dim3(256), 0, c->stream,
-                                       LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv), (const T*)src, lds, vsrc, ldv, f, ldf,
+                                       LevelPtr<T>::stp(lv), (const T*)src, lds, vsrc, ldv, f, ldf,
                                        dst, ldd, nx, width, wl, py, fx, vzero, npairs, nrows);
             }
         }
