@@ -644,6 +644,194 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     }
 }
 
+// One whole four-colour sweep by row phases in one launch (W >= 32 modes).
+// A workgroup owns a segment of one phase-1 row y1 (parity p1) and walks it
+// together with the two phase-0 rows y1 - 1 and y1 + 1 around it: each step
+// relaxes the phase-0 rows at S node s0 and F node s0 + 1 from the old values
+// (rows y1 - 2 .. y1 + 2), then the phase-1 row one step behind, at s0 - 2 and
+// s0 - 1, from the new values of the phase-0 rows kept in registers.  The
+// phase-0 rows are relaxed twice (by the workgroups of y1 and y1 + 2; row 0
+// by the one of y1 = 1) and written once, by the workgroup below them; their
+// walk starts two S nodes left of the segment and ends one right of it so
+// that the phase-1 row has all its new neighbours.  Every node gets exactly
+// the update of k_gs_rows (same formula, same inputs), so a sweep equals its
+// two row-phase launches.  It runs for the first sweep from the zero start
+// (OWNZ: no old values, only f is read), where it replaces two launches and
+// the re-read of the phase-0 rows; with old values to read, its longer step
+// (four relaxations, fourteen loads) ran no faster than the two row-phase
+// launches, which the other sweeps keep.
+template <typename T, bool OWNZ, int SEG>
+__global__ void __launch_bounds__(256) k_gs_sweep(const T* __restrict__ stp, const T* __restrict__ A, int lda,
+                                                  const T* __restrict__ f, int ldf, T* __restrict__ B, int ldb,
+                                                  int nx, int width, int p1, int fx, int nseg, int nrows1) {
+    constexpr int NIT = SEG / 2;                   // phase-1 S nodes per segment
+    constexpr int NJ = NIT + 2;                    // phase-0 steps
+    constexpr int D = 2;                           // steps of loads in flight
+    constexpr int SP = sizeof(T) == 4 ? 12 : 10;  // pitch of a padded stencil (9 + reciprocal diagonal)
+    constexpr int NC = SEG + 8;                    // staged columns sf - 4 .. sf + SEG + 3
+    constexpr int NL = 14;                         // loads per step
+    __shared__ T stl[3 * NC * SP];
+    const int lane = threadIdx.x & 63;
+    const int s_w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = s_w * 64 + lane;
+    const bool ok = t < width;
+    const int tc = ok ? t : width - 1;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    if (lb >= nrows1 * nseg) return;  // uniform over the workgroup
+    const int r = lb / nseg;
+    const int y1 = p1 + 2 * r;
+    const int x0 = (lb - r * nseg) * SEG;
+    const int x1 = min(x0 + SEG, nx);
+    const int sf = x0 + (fx ? 0 : 1);  // first S node of the segment (S parity is 1 - fx)
+    const int cb = sf - 4;             // column of the first staged stencil
+    // stencils of rows y1 - 1, y1, y1 + 1 (clamped into the grid)
+    for (int i = threadIdx.x; i < 3 * NC * SP; i += blockDim.x) {
+        const int rk = i / (NC * SP), rem = i - rk * (NC * SP);
+        const int c = rem / SP, e = rem - c * SP;
+        const int yy = min(max(y1 - 1 + rk, 0), nx - 1), xx = min(max(cb + c, 0), nx - 1);
+        stl[i] = stp[((size_t)yy * nx + xx) * SP + e];
+    }
+    __syncthreads();
+    const bool hasA = y1 >= 1, hasB = y1 + 1 < nx;  // phase-0 rows y1 - 1, y1 + 1
+    const bool writeA = y1 == 1;                     // row 0 has no workgroup below it
+    // old rows y1 - 2 .. y1 + 2 (k = 0..4), f rows y1 - 1 .. y1 + 1, output rows y1 - 1 .. y1 + 1
+    bool rin[5];
+    const T* orow[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int yy = y1 - 2 + k;
+        rin[k] = yy >= 0 && yy < nx;
+        orow[k] = A + (size_t)(rin[k] ? yy : 0) * nx * lda;
+    }
+    const T* frow[3];
+    T* brow[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int yy = min(max(y1 - 1 + k, 0), nx - 1);
+        frow[k] = f + (size_t)yy * nx * ldf;
+        brow[k] = B + (size_t)yy * nx * ldb;
+    }
+    auto cx = [&](int x) { return min(max(x, 0), nx - 1); };
+    auto inx = [&](int x) { return x >= 0 && x < nx; };
+    auto gO = [&](int k, int x) -> T { return OWNZ ? T(0) : (orow[k] + cx(x) * lda)[tc]; };
+    auto zO = [&](T v, int k, int x) -> T { return (!OWNZ && rin[k] && inx(x)) ? v : T(0); };
+    auto gF = [&](int k, int x) -> T { return (frow[k] + cx(x) * ldf)[tc]; };
+    auto relax = [&](int rk, int x, T fv, T wl, T wr, T d0, T d1, T d2, T u0, T u1, T u2) -> T {
+        const T* st = stl + (rk * NC + (x - cb)) * SP;
+        T acc = fv;
+        acc -= st[0] * d0 + st[1] * d1 + st[2] * d2;
+        acc -= st[6] * u0 + st[7] * u1 + st[8] * u2;
+        acc -= st[3] * wl + st[5] * wr;
+        return acc * st[9];
+    };
+    auto put = [&](int rk, int x, T v) {
+        if (ok && x >= x0 && x < x1) (brow[rk] + x * ldb)[t] = v;
+    };
+    // loads of phase-0 step j (s0 = sf - 2 + 2j): old rows 0, 2, 4 at s0 + 1, s0 + 2; the old S
+    // nodes of rows 1, 3 at s0 + 2; f of rows y1 - 1, y1, y1 + 1 at s0, s0 + 1
+    T q[D][NL];
+    auto issue = [&](int j, int slot) {
+        const int s0 = sf - 2 + 2 * j;
+        q[slot][0] = gO(0, s0 + 1);
+        q[slot][1] = gO(0, s0 + 2);
+        q[slot][2] = gO(2, s0 + 1);
+        q[slot][3] = gO(2, s0 + 2);
+        q[slot][4] = gO(4, s0 + 1);
+        q[slot][5] = gO(4, s0 + 2);
+        q[slot][6] = gO(1, s0 + 2);
+        q[slot][7] = gO(3, s0 + 2);
+        q[slot][8] = gF(0, s0);
+        q[slot][9] = gF(0, s0 + 1);
+        q[slot][10] = gF(1, s0);
+        q[slot][11] = gF(1, s0 + 1);
+        q[slot][12] = gF(2, s0);
+        q[slot][13] = gF(2, s0 + 1);
+    };
+    // prologue values: old rows 0, 2, 4 at sf - 4 .. sf - 2, old S of rows 1, 3 at sf - 4, sf - 2,
+    // f of rows y1 -+ 1 at sf - 3
+    T w0[4], w2[4], w4[4];  // old rows 0, 2, 4 at s0 - 1 .. s0 + 2 (before a step: at s0 - 3 .. s0)
+    const T p0 = gO(0, sf - 4), p2 = gO(2, sf - 4), p4 = gO(4, sf - 4);
+    w0[2] = gO(0, sf - 3); w0[3] = gO(0, sf - 2);
+    w2[2] = gO(2, sf - 3); w2[3] = gO(2, sf - 2);
+    w4[2] = gO(4, sf - 3); w4[3] = gO(4, sf - 2);
+    T Sa0 = gO(1, sf - 2), Sb0 = gO(3, sf - 2);
+    const T Sam = gO(1, sf - 4), Sbm = gO(3, sf - 4);
+    const T fa3 = gF(0, sf - 3), fb3 = gF(2, sf - 3);
+#pragma unroll
+    for (int k = 0; k < D; ++k) issue(k, k);
+    w0[2] = zO(w0[2], 0, sf - 3); w0[3] = zO(w0[3], 0, sf - 2);
+    w2[2] = zO(w2[2], 2, sf - 3); w2[3] = zO(w2[3], 2, sf - 2);
+    w4[2] = zO(w4[2], 4, sf - 3); w4[3] = zO(w4[3], 4, sf - 2);
+    Sa0 = zO(Sa0, 1, sf - 2);
+    Sb0 = zO(Sb0, 3, sf - 2);
+    // new F(sf - 3) of the phase-0 rows
+    T FaPrev = T(0), FbPrev = T(0);
+    if (inx(sf - 3)) {
+        const T d0 = zO(p0, 0, sf - 4), d2 = zO(p2, 2, sf - 4), d4 = zO(p4, 4, sf - 4);
+        if (hasA) FaPrev = relax(0, sf - 3, fa3, zO(Sam, 1, sf - 4), Sa0, d0, w0[2], w0[3], d2, w2[2], w2[3]);
+        if (hasB) FbPrev = relax(2, sf - 3, fb3, zO(Sbm, 3, sf - 4), Sb0, d2, w2[2], w2[3], d4, w4[2], w4[3]);
+    }
+    // new values of the phase-0 rows at s0 - 3 .. s0 + 1 (after a step)
+    T nA[5] = {T(0), T(0), T(0), T(0), FaPrev}, nB[5] = {T(0), T(0), T(0), T(0), FbPrev};
+    T s1p = T(0), f1p0 = T(0), f1p1 = T(0), F1prev = T(0);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int k = j % D;
+        const int s0 = sf - 2 + 2 * j;
+        T v[NL];
+#pragma unroll
+        for (int e = 0; e < NL; ++e) v[e] = q[k][e];
+        if (j + D < NJ) issue(j + D, k);
+        // windows move two columns
+        w0[0] = w0[2]; w0[1] = w0[3]; w0[2] = zO(v[0], 0, s0 + 1); w0[3] = zO(v[1], 0, s0 + 2);
+        w2[0] = w2[2]; w2[1] = w2[3]; w2[2] = zO(v[2], 2, s0 + 1); w2[3] = zO(v[3], 2, s0 + 2);
+        w4[0] = w4[2]; w4[1] = w4[3]; w4[2] = zO(v[4], 4, s0 + 1); w4[3] = zO(v[5], 4, s0 + 2);
+        const T Sa2 = zO(v[6], 1, s0 + 2), Sb2 = zO(v[7], 3, s0 + 2);
+        // phase 0: F(s0 + 1) from the old S(s0), S(s0 + 2); then S(s0) from the new F(s0 - 1), F(s0 + 1)
+        T Fa = T(0), Sa = T(0), Fb = T(0), Sb = T(0);
+        if (hasA) {
+            if (inx(s0 + 1)) Fa = relax(0, s0 + 1, v[9], Sa0, Sa2, w0[1], w0[2], w0[3], w2[1], w2[2], w2[3]);
+            if (inx(s0)) Sa = relax(0, s0, v[8], FaPrev, Fa, w0[0], w0[1], w0[2], w2[0], w2[1], w2[2]);
+            if (writeA) {
+                put(0, s0 + 1, Fa);
+                put(0, s0, Sa);
+            }
+        }
+        if (hasB) {
+            if (inx(s0 + 1)) Fb = relax(2, s0 + 1, v[13], Sb0, Sb2, w2[1], w2[2], w2[3], w4[1], w4[2], w4[3]);
+            if (inx(s0)) Sb = relax(2, s0, v[12], FbPrev, Fb, w2[0], w2[1], w2[2], w4[0], w4[1], w4[2]);
+            put(2, s0 + 1, Fb);
+            put(2, s0, Sb);
+        }
+        nA[0] = nA[2]; nA[1] = nA[3]; nA[2] = nA[4]; nA[3] = Sa; nA[4] = Fa;
+        nB[0] = nB[2]; nB[1] = nB[3]; nB[2] = nB[4]; nB[3] = Sb; nB[4] = Fb;
+        // phase 1, one step behind: the new phase-0 rows at s0 - 3 .. s0 are final
+        if (j == 1) {
+            // new F(sf - 1) from the old S(sf - 2), S(sf)
+            if (inx(sf - 1)) {
+                F1prev = relax(1, sf - 1, f1p1, s1p, w2[1], nA[1], nA[2], nA[3], nB[1], nB[2], nB[3]);
+                put(1, sf - 1, F1prev);
+            }
+        } else if (j >= 2) {
+            const int s = s0 - 2;
+            T F1 = T(0);
+            if (inx(s + 1)) {
+                F1 = relax(1, s + 1, f1p1, s1p, w2[1], nA[1], nA[2], nA[3], nB[1], nB[2], nB[3]);
+                put(1, s + 1, F1);
+            }
+            if (inx(s)) put(1, s, relax(1, s, f1p0, F1prev, F1, nA[0], nA[1], nA[2], nB[0], nB[1], nB[2]));
+            F1prev = F1;
+        }
+        s1p = w2[1];  // old S(s0) of row y1
+        f1p0 = v[10];
+        f1p1 = v[11];
+        Sa0 = Sa2;
+        Sb0 = Sb2;
+        FaPrev = Fa;
+        FbPrev = Fb;
+    }
+}
+
 // Row-phase Gauss-Seidel for narrow blocks (W <= 32 modes): the same update
 // as k_gs_rows without the walk.  A lane owns, for one mode, the S node s of
 // a row and the F node s + 1, and recomputes the F node s - 1 that its S
@@ -1433,23 +1621,33 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
         }
         // forward: rows y odd (fx = 1), then y even (fx = 1); backward: y even (fx = 0), then y odd (fx = 0)
         const int py1 = reverse ? 0 : 1, fx = reverse ? 0 : 1;
-        for (int ph = 0; ph < 2; ++ph) {
-            const int py = ph == 0 ? py1 : 1 - py1;
-            const int nrows = (nx - py + 1) / 2;
-            const T* vsrc = ph == 0 ? src : dst;
-            const int ldv = ph == 0 ? lds : ldd;
-            const int vzero = (ph == 0 && own_zero) ? 1 : 0;
-            if (width >= 32) {
-                auto go = [&](auto kern) {
-                    hipLaunchKernelGGL(kern, dim3(nrows * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv),
-                                       LevelPtr<T>::rd(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py, fx, vzero, nseg,
-                                       nrows);
-                };
-                if (own_zero)
-                    shortw ? go(k_gs_rows<T, true, kRowSegShort>) : go(k_gs_rows<T, true, kRowSeg>);
-                else
-                    shortw ? go(k_gs_rows<T, false, kRowSegShort>) : go(k_gs_rows<T, false, kRowSeg>);
-            } else {
+        if (width >= 32 && own_zero) {
+            // the first sweep from the zero start: both row phases in one launch (only f is read)
+            const int p1 = 1 - py1;
+            const int nrows1 = (nx - p1 + 1) / 2;
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(nrows1 * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::stp(lv),
+                                   (const T*)src, lds, f, ldf, dst, ldd, nx, width, p1, fx, nseg, nrows1);
+            };
+            shortw ? go(k_gs_sweep<T, true, kRowSegShort>) : go(k_gs_sweep<T, true, kRowSeg>);
+        } else if (width >= 32) {
+            for (int ph = 0; ph < 2; ++ph) {
+                const int py = ph == 0 ? py1 : 1 - py1;
+                const int nrows = (nx - py + 1) / 2;
+                const T* vsrc = ph == 0 ? src : dst;
+                const int ldv = ph == 0 ? lds : ldd;
+                hipLaunchKernelGGL((shortw ? k_gs_rows<T, false, kRowSegShort> : k_gs_rows<T, false, kRowSeg>),
+                                   dim3(nrows * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv),
+                                   LevelPtr<T>::rd(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py,
+                                   fx, 0, nseg, nrows);
+            }
+        } else {
+            for (int ph = 0; ph < 2; ++ph) {
+                const int py = ph == 0 ? py1 : 1 - py1;
+                const int nrows = (nx - py + 1) / 2;
+                const T* vsrc = ph == 0 ? src : dst;
+                const int ldv = ph == 0 ? lds : ldd;
+                const int vzero = (ph == 0 && own_zero) ? 1 : 0;
                 int wl = 0;
                 while ((1 << wl) < width) ++wl;
                 const int npairs = fx ? (nx - 1) / 2 + 1 : nx / 2 + 1;  // pairs (S(s), F(s+1)) covering the row
