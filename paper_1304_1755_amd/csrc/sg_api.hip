@@ -69,8 +69,13 @@ int upload_plan(sg_ctx* c, const PlanHost& ph, Plan& pl) {
     if (!rc) rc = upload(c, &pl.d_xcoef, ph.xcoef);
     if (!rc) rc = upload(c, &pl.d_npos, ph.npos);
     if (!rc) rc = upload(c, &pl.d_off, ph.off);
-    if (rc) return rc;
-    return upload(c, &pl.d_coef, ph.coef);
+    if (!rc) rc = upload(c, &pl.d_coef, ph.coef);
+    pl.one_partner = ph.one_partner;
+    pl.d_okb = nullptr;
+    pl.d_ocoef = nullptr;
+    if (!rc && ph.one_partner) rc = upload(c, &pl.d_okb, ph.okb);
+    if (!rc && ph.one_partner) rc = upload(c, &pl.d_ocoef, ph.ocoef);
+    return rc;
 }
 
 size_t NP(const sg_ctx* c) { return (size_t)c->hs.N * c->hs.P; }

@@ -83,6 +83,11 @@ struct PlanHost {
     std::vector<int> npos;        // nslot
     std::vector<uint32_t> off;    // nslot*64*m   (gradient tables)
     std::vector<double> coef;     // nslot*64*2m
+    // when every output mode has at most one partner (one_partner): per output mode its
+    // coefficient row k+1 | input lane << 8 and coefficient (0: none)
+    int one_partner = 0;
+    std::vector<int> okb;
+    std::vector<double> ocoef;
 };
 PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_out, bool self, bool up, bool down);
 
@@ -95,6 +100,9 @@ struct Plan {
     int nblk_max;  // max over slots of ceil(npos / 4)
     uint32_t* d_off;
     double* d_coef;
+    int one_partner;
+    int* d_okb;
+    double* d_ocoef;
 };
 
 struct Level {

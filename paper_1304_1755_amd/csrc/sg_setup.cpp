@@ -443,6 +443,22 @@ PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_o
                 parts[t].push_back({k, dir, it->second - in_lo, dir == 0 ? al[k] + 1 : al[k]});
             }
     }
+    // single-partner table (the first degree level's lower coupling: e_k from the mean mode)
+    {
+        size_t most = 0;
+        for (int t = 0; t < W_out; ++t) most = std::max(most, parts[t].size());
+        if (most <= 1 && !self) {
+            pl.one_partner = 1;
+            pl.okb.assign(W_out, 0);  // no partner: coefficient row 0 (valid) with coefficient 0
+            pl.ocoef.assign(W_out, 0.0);
+            for (int t = 0; t < W_out; ++t)
+                if (!parts[t].empty()) {
+                    const Partner& q = parts[t][0];
+                    pl.okb[t] = (q.k + 1) | (q.b << 8);
+                    pl.ocoef[t] = hs.gscale * legendre_b(q.key);
+                }
+        }
+    }
     // gradient tables: fixed positions 2k (up) and 2k+1 (down) per lane
     const uint32_t gzero = (uint32_t)(m * lanes);
     pl.off.assign((size_t)lanes * (L / 2), gzero | (gzero << 16));
