@@ -24,8 +24,9 @@
 // Kernel forms by block width W (modes) and grid size:
 //   * four-colour smoothing runs as row phases (one launch per row parity,
 //     both colours of a row): for W >= 32 a workgroup walks a row segment
-//     with lanes over modes (k_gs_rows); narrower blocks give each lane one
-//     (row, S node, mode) triple (k_gs_rows_narrow);
+//     with lanes over modes (k_gs_rows; the first sweep from the zero start
+//     takes both phases in one launch, k_gs_sweep); narrower blocks give each
+//     lane one (row, S node, mode) triple (k_gs_rows_narrow);
 //   * for W >= 16 residual + restriction is one walking pass
 //     (k_resid_restrict) and the prolongation another (k_prolong_rows);
 //     narrower blocks use one node per thread (k_residual, k_restrict,
@@ -33,8 +34,11 @@
 //   * walking kernels use short segments on coarse grids, where long walks
 //     would leave too few wavefronts;
 //   * grids of at most 63 x 63 (float) or 31 x 31 (double) interior nodes are
-//     cycled by one launch that keeps them in LDS (k_vcycle_fused4;
-//     k_vcycle_fused for red/black).
+//     cycled by one launch that keeps them in LDS (k_vcycle_pad for grids of
+//     2^k - 1 nodes per side, k_vcycle_fused4 for other four-colour
+//     hierarchies, k_vcycle_fused for red/black and lexicographic);
+//   * the finest level iterates in its own compact block; only the last
+//     post-smoothing sweep writes the caller's (possibly strided) output.
 
 #include "sg_internal.h"
 
