@@ -836,6 +836,184 @@ __global__ void __launch_bounds__(256) k_gs_sweep(const T* __restrict__ stp, con
     }
 }
 
+// ------------------------------------------------------------ one right-hand side
+// The degree-0 block of B_T has a single mode: its cycle on the large grids is
+// a chain of short launches.  These two kernels cut it to two launches per
+// level.  A workgroup of 1024 threads owns a tile of kTileCX x kTileCY coarse
+// nodes and keeps the 64 x 64 fine nodes around the tile's fine core in LDS
+// (with a border of zeros), one 2 x 2 block of nodes per thread, so each
+// thread owns one node of every colour and holds its four stencils in
+// registers.  A four-colour sweep is four colour passes in LDS; the values
+// near the region's edge go stale (their neighbours outside are not
+// updated), but the stale band grows by at most two nodes in x and one in y
+// per row phase (the row-phase sweeps of k_gs_rows_narrow update a row's F
+// nodes from old S nodes, then its S nodes), so with nu <= 2 the fine core
+// plus one ring is exact.  Down: nu1 forward sweeps from zero, the residual on
+// the core plus one ring, R = P^T into the coarse right-hand side, and the
+// smoothed core written out.  Up: the smoothed values plus P e over the
+// region, nu2 backward sweeps, the core written out.  Every relaxation,
+// residual, restriction and prolongation has the formula of the multi-launch
+// path (k_gs_rows_narrow, k_residual, k_restrict, k_prolong_add).
+constexpr int kTileCX = 22, kTileCY = 26;  // coarse nodes per tile
+constexpr int kTileHX = 10, kTileHY = 6;   // fine halo of the region in x, y
+constexpr int kTileR = 64;                 // region side: 2 * 22 + 2 * 10 = 2 * 26 + 2 * 6 = 64
+constexpr int kTileP = kTileR + 2;         // with the border of zeros
+constexpr int kTileMaxNu = 2;              // sweeps the halo covers
+
+template <typename T>
+struct TileOwn {
+    T st[4][9];
+    T rd[4];
+    T f[4];
+    bool in[4];  // the node lies in the grid
+};
+
+// thread t owns block (t % 32, t / 32); its node of colour q (x odd for q even,
+// y odd for q < 2) at region coordinates (lx, ly)
+__device__ __forceinline__ void tile_node(int q, int t, int& lx, int& ly) {
+    lx = 2 * (t & 31) + ((q & 1) ^ 1);
+    ly = 2 * (t >> 5) + ((q >> 1) ^ 1);
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_load(const T* __restrict__ stp, const T* __restrict__ f, int ldf, int nx, int rx0,
+                                          int ry0, TileOwn<T>& on) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int lx, ly;
+        tile_node(q, threadIdx.x, lx, ly);
+        const int gx = rx0 + lx, gy = ry0 + ly;
+        on.in[q] = gx >= 0 && gx < nx && gy >= 0 && gy < nx;
+        const size_t node = on.in[q] ? (size_t)gy * nx + gx : 0;
+        const T* e = stp + node * (sizeof(T) == 4 ? 12 : 10);
+        if constexpr (sizeof(T) == 4) {
+            const float4 a = ((const float4*)e)[0], b = ((const float4*)e)[1], c = ((const float4*)e)[2];
+            on.st[q][0] = a.x; on.st[q][1] = a.y; on.st[q][2] = a.z; on.st[q][3] = a.w;
+            on.st[q][4] = b.x; on.st[q][5] = b.y; on.st[q][6] = b.z; on.st[q][7] = b.w;
+            on.st[q][8] = c.x; on.rd[q] = c.y;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const double2 v = ((const double2*)e)[k];
+                on.st[q][2 * k] = v.x;
+                if (k < 4) on.st[q][2 * k + 1] = v.y; else on.rd[q] = v.y;
+            }
+        }
+        on.f[q] = f[node * ldf];
+    }
+}
+
+// colour passes of nu sweeps on the padded region u (forward: colours 0..3)
+template <typename T>
+__device__ __forceinline__ void tile_sweeps(const TileOwn<T>& on, T* u, int nu, bool reverse) {
+    for (int sw = 0; sw < nu; ++sw)
+#pragma unroll
+        for (int qi = 0; qi < 4; ++qi) {
+            const int q = reverse ? 3 - qi : qi;
+            int lx, ly;
+            tile_node(q, threadIdx.x, lx, ly);
+            T* c = u + (ly + 1) * kTileP + lx + 1;
+            if (on.in[q]) {
+                const T* s = on.st[q];
+                T acc = on.f[q];
+                acc -= s[0] * c[-kTileP - 1] + s[1] * c[-kTileP] + s[2] * c[-kTileP + 1];
+                acc -= s[6] * c[kTileP - 1] + s[7] * c[kTileP] + s[8] * c[kTileP + 1];
+                acc -= s[3] * c[-1] + s[5] * c[1];
+                *c = acc * on.rd[q];
+            }
+            __syncthreads();
+        }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_cycle1_down(const T* __restrict__ stp, const T* __restrict__ f, int ldf,
+                                                      T* __restrict__ uo, int ldo, T* __restrict__ fc, int ldc, int nx,
+                                                      int nu, int ntx, int p1) {
+    __shared__ T u[kTileP * kTileP];
+    __shared__ T r[(2 * kTileCX + 1) * (2 * kTileCY + 1)];
+    const int nxc = (nx - 1) / 2;
+    const int X0 = (blockIdx.x % ntx) * kTileCX, Y0 = (blockIdx.x / ntx) * kTileCY;
+    const int rx0 = 2 * X0 - kTileHX, ry0 = 2 * Y0 - kTileHY;
+    for (int i = threadIdx.x; i < kTileP * kTileP; i += blockDim.x) u[i] = T(0);  // zero start and border
+    TileOwn<T> on;
+    tile_load<T>(stp, f, ldf, nx, rx0, ry0, on);
+    __syncthreads();
+    tile_sweeps<T>(on, u, nu, false);
+    // residual at fine nodes 2 X0 .. 2 X0 + 2 kTileCX (and y alike), the formula of k_residual
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int lx, ly;
+        tile_node(q, threadIdx.x, lx, ly);
+        const int ax = rx0 + lx - 2 * X0, ay = ry0 + ly - 2 * Y0;
+        if (on.in[q] && ax >= 0 && ax <= 2 * kTileCX && ay >= 0 && ay <= 2 * kTileCY) {
+            const T* c = u + (ly + 1) * kTileP + lx + 1;
+            T acc = on.f[q];
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) acc -= on.st[q][(dy + 1) * 3 + (dx + 1)] * c[dy * kTileP + dx];
+            r[ay * (2 * kTileCX + 1) + ax] = acc;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTileCX * kTileCY; i += blockDim.x) {
+        const int X = X0 + i % kTileCX, Y = Y0 + i / kTileCX;
+        if (X < nxc && Y < nxc)
+            fc[((size_t)Y * nxc + X) * ldc] = restrict_value<T>(
+                [&](int x, int y) { return r[(y - 2 * Y0) * (2 * kTileCX + 1) + (x - 2 * X0)]; }, X, Y, p1 != 0);
+    }
+    // the smoothed core (the last tile of a row or column also owns the grid's last node)
+    const int cx1 = X0 + kTileCX >= nxc ? nx : 2 * (X0 + kTileCX);
+    const int cy1 = Y0 + kTileCY >= nxc ? nx : 2 * (Y0 + kTileCY);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int lx, ly;
+        tile_node(q, threadIdx.x, lx, ly);
+        const int gx = rx0 + lx, gy = ry0 + ly;
+        if (gx >= 2 * X0 && gx < cx1 && gy >= 2 * Y0 && gy < cy1)
+            uo[((size_t)gy * nx + gx) * ldo] = u[(ly + 1) * kTileP + lx + 1];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_cycle1_up(const T* __restrict__ stp, const T* __restrict__ f, int ldf,
+                                                    const T* __restrict__ ui, int ldi, const T* __restrict__ ec,
+                                                    int ldc, T* __restrict__ uo, int ldo, int nx, int nu, int ntx,
+                                                    int p1) {
+    __shared__ T u[kTileP * kTileP];
+    const int nxc = (nx - 1) / 2;
+    const int X0 = (blockIdx.x % ntx) * kTileCX, Y0 = (blockIdx.x / ntx) * kTileCY;
+    const int rx0 = 2 * X0 - kTileHX, ry0 = 2 * Y0 - kTileHY;
+    for (int i = threadIdx.x; i < kTileP * kTileP; i += blockDim.x) u[i] = T(0);  // border (and nodes outside the grid)
+    TileOwn<T> on;
+    tile_load<T>(stp, f, ldf, nx, rx0, ry0, on);
+    __syncthreads();
+    // smoothed values plus the prolonged correction, the formula of k_prolong_add
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int lx, ly;
+        tile_node(q, threadIdx.x, lx, ly);
+        const int gx = rx0 + lx, gy = ry0 + ly;
+        if (on.in[q]) {
+            T v = ui[((size_t)gy * nx + gx) * ldi];
+            v += prolong_value<T>([&](int X, int Y) { return ec[((size_t)Y * nxc + X) * ldc]; }, nxc, gx, gy, p1 != 0);
+            u[(ly + 1) * kTileP + lx + 1] = v;
+        }
+    }
+    __syncthreads();
+    tile_sweeps<T>(on, u, nu, true);
+    const int cx1 = X0 + kTileCX >= nxc ? nx : 2 * (X0 + kTileCX);
+    const int cy1 = Y0 + kTileCY >= nxc ? nx : 2 * (Y0 + kTileCY);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int lx, ly;
+        tile_node(q, threadIdx.x, lx, ly);
+        const int gx = rx0 + lx, gy = ry0 + ly;
+        if (gx >= 2 * X0 && gx < cx1 && gy >= 2 * Y0 && gy < cy1)
+            uo[((size_t)gy * nx + gx) * ldo] = u[(ly + 1) * kTileP + lx + 1];
+    }
+}
+
 // Row-phase Gauss-Seidel for narrow blocks (W <= 32 modes): the same update
 // as k_gs_rows without the walk.  A lane owns, for one mode, the S node s of
 // a row and the F node s + 1, and recomputes the F node s - 1 that its S
@@ -1705,6 +1883,94 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     auto fld = [&](int l) { return l == 0 ? ldf0 : width; };
     auto uptr = [&](int l) -> T* { return l == 0 ? uc0 : LevelPtr<T>::u(c->levels[l]); };
     auto uld = [&](int l) { return l == 0 ? ldc0 : width; };
+    // the coarse part: the fused LDS cycle from level Lc, or the coarsest solve at level L
+    auto coarse_part = [&]() -> int {
+        bool pad = Lc >= 0 && c->opt.colour_mode == SG_COLOUR_FOUR && L - Lc + 1 <= kMaxFusedLevels;
+        for (int l = Lc; pad && l < L; ++l)
+            pad = pad_cycle_size(c->levels[l].nx) && LevelPtr<T>::cst(c->levels[l]) != nullptr;
+        if (pad) {
+            PadLevels<T> pl{};
+            pl.nlev = L - Lc + 1;
+            pl.p1 = p1;
+            int off = 0;
+            for (int i = 0; i < pl.nlev; ++i) {
+                const Level& lv = c->levels[Lc + i];
+                pl.nx[i] = lv.nx;
+                pl.uoff[i] = off;
+                off += (lv.nx + 2) * (lv.nx + 2);
+                pl.foff[i] = off;
+                off += lv.N;
+                pl.cst[i] = LevelPtr<T>::cst(lv);
+            }
+            pl.roff = off;
+            off += c->levels[Lc].N;
+            hipLaunchKernelGGL(k_vcycle_pad<T>, dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T), c->stream,
+                               pl, (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2);
+        } else if (Lc >= 0) {
+            FusedLevels<T> fl{};
+            fl.nlev = L - Lc + 1;
+            if (fl.nlev > kMaxFusedLevels) {
+                set_error("vcycle: too many coarse levels");
+                return SG_EINVAL;
+            }
+            int off = 0;
+            for (int i = 0; i < fl.nlev; ++i) {
+                const Level& lv = c->levels[Lc + i];
+                fl.nx[i] = lv.nx;
+                fl.off[i] = off;
+                fl.sten[i] = LevelPtr<T>::s(lv);
+                fl.rdiag[i] = LevelPtr<T>::rd(lv);
+                off += 2 * lv.N;
+            }
+            fl.roff = off;
+            fl.p1 = p1;
+            off += c->levels[Lc].N;
+            if (c->opt.colour_mode == SG_COLOUR_FOUR)
+                hipLaunchKernelGGL(k_vcycle_fused4<T>, dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T),
+                                   c->stream, fl,
+                                   (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2);
+            else
+                hipLaunchKernelGGL(k_vcycle_fused<T>, dim3(width), dim3(512), (size_t)off * sizeof(T), c->stream, fl,
+                                   (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2,
+                                   c->opt.colour_mode == SG_COLOUR_LEX ? 2 : 1);
+        } else {
+            Level& lc = c->levels[L];
+            hipLaunchKernelGGL(k_coarse<T>, dim3(width), dim3(256), (size_t)lc.N * sizeof(double), c->stream, c->kinv,
+                               fptr(L), fld(L), uptr(L), uld(L), lc.N);
+        }
+        return SG_OK;
+    };
+    if (width == 1 && c->opt.colour_mode == SG_COLOUR_FOUR && c->opt.nu1 <= kTileMaxNu &&
+        c->opt.nu2 <= kTileMaxNu && Ltop > 0) {
+        // a single mode: two tile launches per level above the coarse part; the
+        // smoothed values of level l go to uptr(l), the corrected ones to the
+        // level's second buffer (u0 on the finest level)
+        auto tiles = [&](const Level& lv, int& ntx) {
+            const int nxc = (lv.nx - 1) / 2;
+            ntx = (nxc + kTileCX - 1) / kTileCX;
+            return ntx * ((nxc + kTileCY - 1) / kTileCY);
+        };
+        for (int l = 0; l < Ltop; ++l) {
+            Level& lv = c->levels[l];
+            int ntx;
+            const int nb = tiles(lv, ntx);
+            hipLaunchKernelGGL(k_cycle1_down<T>, dim3(nb), dim3(1024), 0, c->stream, LevelPtr<T>::stp(lv), fptr(l),
+                               fld(l), uptr(l), uld(l), LevelPtr<T>::f(c->levels[l + 1]), 1, lv.nx, c->opt.nu1, ntx,
+                               (int)p1);
+        }
+        if (int rc = coarse_part()) return rc;
+        for (int l = Ltop - 1; l >= 0; --l) {
+            Level& lv = c->levels[l];
+            int ntx;
+            const int nb = tiles(lv, ntx);
+            const T* ec = l + 1 == Ltop ? uptr(Ltop) : LevelPtr<T>::u2(c->levels[l + 1]);
+            T* out = l == 0 ? u0 : LevelPtr<T>::u2(lv);
+            hipLaunchKernelGGL(k_cycle1_up<T>, dim3(nb), dim3(1024), 0, c->stream, LevelPtr<T>::stp(lv), fptr(l),
+                               fld(l), (const T*)uptr(l), uld(l), ec, 1, out, l == 0 ? ldu0 : 1, lv.nx, c->opt.nu2,
+                               ntx, (int)p1);
+        }
+        return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
+    }
     for (int l = 0; l < Ltop; ++l) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
@@ -1738,59 +2004,7 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
                                (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width, (int)p1);
         }
     }
-    bool pad = Lc >= 0 && c->opt.colour_mode == SG_COLOUR_FOUR && L - Lc + 1 <= kMaxFusedLevels;
-    for (int l = Lc; pad && l < L; ++l)
-        pad = pad_cycle_size(c->levels[l].nx) && LevelPtr<T>::cst(c->levels[l]) != nullptr;
-    if (pad) {
-        PadLevels<T> pl{};
-        pl.nlev = L - Lc + 1;
-        pl.p1 = p1;
-        int off = 0;
-        for (int i = 0; i < pl.nlev; ++i) {
-            const Level& lv = c->levels[Lc + i];
-            pl.nx[i] = lv.nx;
-            pl.uoff[i] = off;
-            off += (lv.nx + 2) * (lv.nx + 2);
-            pl.foff[i] = off;
-            off += lv.N;
-            pl.cst[i] = LevelPtr<T>::cst(lv);
-        }
-        pl.roff = off;
-        off += c->levels[Lc].N;
-        hipLaunchKernelGGL(k_vcycle_pad<T>, dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T), c->stream,
-                           pl, (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2);
-    } else if (Lc >= 0) {
-        FusedLevels<T> fl{};
-        fl.nlev = L - Lc + 1;
-        if (fl.nlev > kMaxFusedLevels) {
-            set_error("vcycle: too many coarse levels");
-            return SG_EINVAL;
-        }
-        int off = 0;
-        for (int i = 0; i < fl.nlev; ++i) {
-            const Level& lv = c->levels[Lc + i];
-            fl.nx[i] = lv.nx;
-            fl.off[i] = off;
-            fl.sten[i] = LevelPtr<T>::s(lv);
-            fl.rdiag[i] = LevelPtr<T>::rd(lv);
-            off += 2 * lv.N;
-        }
-        fl.roff = off;
-        fl.p1 = p1;
-        off += c->levels[Lc].N;
-        if (c->opt.colour_mode == SG_COLOUR_FOUR)
-            hipLaunchKernelGGL(k_vcycle_fused4<T>, dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T),
-                               c->stream, fl,
-                               (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2);
-        else
-            hipLaunchKernelGGL(k_vcycle_fused<T>, dim3(width), dim3(512), (size_t)off * sizeof(T), c->stream, fl,
-                               (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2,
-                               c->opt.colour_mode == SG_COLOUR_LEX ? 2 : 1);
-    } else {
-        Level& lc = c->levels[L];
-        hipLaunchKernelGGL(k_coarse<T>, dim3(width), dim3(256), (size_t)lc.N * sizeof(double), c->stream, c->kinv,
-                           fptr(L), fld(L), uptr(L), uld(L), lc.N);
-    }
+    if (int rc = coarse_part()) return rc;
     for (int l = Ltop - 1; l >= 0; --l) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
