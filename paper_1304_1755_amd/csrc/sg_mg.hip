@@ -837,10 +837,11 @@ __global__ void __launch_bounds__(256) k_gs_sweep(const T* __restrict__ stp, con
 }
 
 // ------------------------------------------------------------ one right-hand side
-// The degree-0 block of B_T has a single mode: its cycle on the large grids is
-// a chain of short launches.  These two kernels cut it to two launches per
-// level.  A workgroup of 1024 threads owns a tile of kTileCX x kTileCY coarse
-// nodes and keeps the 64 x 64 fine nodes around the tile's fine core in LDS
+// The narrowest blocks of B_T (one mode at degree 0, a few at degree 1) cycle
+// on the large grids as chains of short launches.  These two kernels cut the
+// cycle to two launches per level.  A workgroup of 1024 threads owns one mode
+// of a tile of kTileCX x kTileCY coarse nodes (a launch covers every tile and
+// mode) and keeps the 64 x 64 fine nodes around the tile's fine core in LDS
 // (with a border of zeros), one 2 x 2 block of nodes per thread, so each
 // thread owns one node of every colour and holds its four stencils in
 // registers.  A four-colour sweep is four colour passes in LDS; the values
@@ -903,7 +904,7 @@ __device__ __forceinline__ void tile_load(const T* __restrict__ stp, const T* __
     }
 }
 
-// colour passes of nu sweeps on the padded region u (forward: colours 0..3)
+// colour passes of nu sweeps on the padded region (forward: colours 0..3)
 template <typename T>
 __device__ __forceinline__ void tile_sweeps(const TileOwn<T>& on, T* u, int nu, bool reverse) {
     for (int sw = 0; sw < nu; ++sw)
@@ -912,9 +913,9 @@ __device__ __forceinline__ void tile_sweeps(const TileOwn<T>& on, T* u, int nu, 
             const int q = reverse ? 3 - qi : qi;
             int lx, ly;
             tile_node(q, threadIdx.x, lx, ly);
-            T* c = u + (ly + 1) * kTileP + lx + 1;
             if (on.in[q]) {
                 const T* s = on.st[q];
+                T* c = u + (ly + 1) * kTileP + lx + 1;
                 T acc = on.f[q];
                 acc -= s[0] * c[-kTileP - 1] + s[1] * c[-kTileP] + s[2] * c[-kTileP + 1];
                 acc -= s[6] * c[kTileP - 1] + s[7] * c[kTileP] + s[8] * c[kTileP + 1];
@@ -925,14 +926,20 @@ __device__ __forceinline__ void tile_sweeps(const TileOwn<T>& on, T* u, int nu, 
         }
 }
 
+// workgroup b: tile b % ntiles of mode b / ntiles (pointers address mode 0)
 template <typename T>
 __global__ void __launch_bounds__(1024) k_cycle1_down(const T* __restrict__ stp, const T* __restrict__ f, int ldf,
                                                       T* __restrict__ uo, int ldo, T* __restrict__ fc, int ldc, int nx,
-                                                      int nu, int ntx, int p1) {
+                                                      int nu, int ntx, int ntiles, int p1) {
     __shared__ T u[kTileP * kTileP];
     __shared__ T r[(2 * kTileCX + 1) * (2 * kTileCY + 1)];
+    constexpr int RW = 2 * kTileCX + 1;
+    const int mode = blockIdx.x / ntiles, tile = blockIdx.x - mode * ntiles;
+    f += mode;
+    uo += mode;
+    fc += mode;
     const int nxc = (nx - 1) / 2;
-    const int X0 = (blockIdx.x % ntx) * kTileCX, Y0 = (blockIdx.x / ntx) * kTileCY;
+    const int X0 = (tile % ntx) * kTileCX, Y0 = (tile / ntx) * kTileCY;
     const int rx0 = 2 * X0 - kTileHX, ry0 = 2 * Y0 - kTileHY;
     for (int i = threadIdx.x; i < kTileP * kTileP; i += blockDim.x) u[i] = T(0);  // zero start and border
     TileOwn<T> on;
@@ -952,7 +959,7 @@ __global__ void __launch_bounds__(1024) k_cycle1_down(const T* __restrict__ stp,
             for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) acc -= on.st[q][(dy + 1) * 3 + (dx + 1)] * c[dy * kTileP + dx];
-            r[ay * (2 * kTileCX + 1) + ax] = acc;
+            r[ay * RW + ax] = acc;
         }
     }
     __syncthreads();
@@ -960,7 +967,7 @@ __global__ void __launch_bounds__(1024) k_cycle1_down(const T* __restrict__ stp,
         const int X = X0 + i % kTileCX, Y = Y0 + i / kTileCX;
         if (X < nxc && Y < nxc)
             fc[((size_t)Y * nxc + X) * ldc] = restrict_value<T>(
-                [&](int x, int y) { return r[(y - 2 * Y0) * (2 * kTileCX + 1) + (x - 2 * X0)]; }, X, Y, p1 != 0);
+                [&](int x, int y) { return r[(y - 2 * Y0) * RW + (x - 2 * X0)]; }, X, Y, p1 != 0);
     }
     // the smoothed core (the last tile of a row or column also owns the grid's last node)
     const int cx1 = X0 + kTileCX >= nxc ? nx : 2 * (X0 + kTileCX);
@@ -979,12 +986,17 @@ template <typename T>
 __global__ void __launch_bounds__(1024) k_cycle1_up(const T* __restrict__ stp, const T* __restrict__ f, int ldf,
                                                     const T* __restrict__ ui, int ldi, const T* __restrict__ ec,
                                                     int ldc, T* __restrict__ uo, int ldo, int nx, int nu, int ntx,
-                                                    int p1) {
+                                                    int ntiles, int p1) {
     __shared__ T u[kTileP * kTileP];
+    const int mode = blockIdx.x / ntiles, tile = blockIdx.x - mode * ntiles;
+    f += mode;
+    ui += mode;
+    ec += mode;
+    uo += mode;
     const int nxc = (nx - 1) / 2;
-    const int X0 = (blockIdx.x % ntx) * kTileCX, Y0 = (blockIdx.x / ntx) * kTileCY;
+    const int X0 = (tile % ntx) * kTileCX, Y0 = (tile / ntx) * kTileCY;
     const int rx0 = 2 * X0 - kTileHX, ry0 = 2 * Y0 - kTileHY;
-    for (int i = threadIdx.x; i < kTileP * kTileP; i += blockDim.x) u[i] = T(0);  // border (and nodes outside the grid)
+    for (int i = threadIdx.x; i < kTileP * kTileP; i += blockDim.x) u[i] = T(0);  // border, nodes outside the grid
     TileOwn<T> on;
     tile_load<T>(stp, f, ldf, nx, rx0, ry0, on);
     __syncthreads();
@@ -1862,6 +1874,21 @@ bool use_row_sweeps(const sg_ctx* c, int width) {
     return c->opt.colour_mode == SG_COLOUR_FOUR;
 }
 
+// block widths the tile cycle takes: a workgroup per (tile, mode), so the
+// launch holds width times the tiles; wider blocks keep the row-phase kernels
+constexpr int kTileMaxWidth = 8;
+
+template <typename T>
+void launch_tile(bool down, int width, int ntiles, hipStream_t st, const T* stp, const T* f, int ldf, const T* ui,
+                 int ldi, const T* ec, int ldc, T* uo, int ldo, T* fc, int ldfc, int nx, int nu, int ntx, int p1) {
+    if (down)
+        hipLaunchKernelGGL(k_cycle1_down<T>, dim3(ntiles * width), dim3(1024), 0, st, stp, f, ldf, uo, ldo, fc, ldfc,
+                           nx, nu, ntx, ntiles, p1);
+    else
+        hipLaunchKernelGGL(k_cycle1_up<T>, dim3(ntiles * width), dim3(1024), 0, st, stp, f, ldf, ui, ldi, ec, ldc, uo,
+                           ldo, nx, nu, ntx, ntiles, p1);
+}
+
 template <typename T>
 int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     const Tile tl = tile_for(width);
@@ -1940,9 +1967,9 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
         }
         return SG_OK;
     };
-    if (width == 1 && c->opt.colour_mode == SG_COLOUR_FOUR && c->opt.nu1 <= kTileMaxNu &&
+    if (width <= kTileMaxWidth && c->opt.colour_mode == SG_COLOUR_FOUR && c->opt.nu1 <= kTileMaxNu &&
         c->opt.nu2 <= kTileMaxNu && Ltop > 0) {
-        // a single mode: two tile launches per level above the coarse part; the
+        // a few modes: two tile launches per level above the coarse part; the
         // smoothed values of level l go to uptr(l), the corrected ones to the
         // level's second buffer (u0 on the finest level)
         auto tiles = [&](const Level& lv, int& ntx) {
@@ -1954,9 +1981,8 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             Level& lv = c->levels[l];
             int ntx;
             const int nb = tiles(lv, ntx);
-            hipLaunchKernelGGL(k_cycle1_down<T>, dim3(nb), dim3(1024), 0, c->stream, LevelPtr<T>::stp(lv), fptr(l),
-                               fld(l), uptr(l), uld(l), LevelPtr<T>::f(c->levels[l + 1]), 1, lv.nx, c->opt.nu1, ntx,
-                               (int)p1);
+            launch_tile<T>(true, width, nb, c->stream, LevelPtr<T>::stp(lv), fptr(l), fld(l), nullptr, 0, nullptr, 0,
+                           uptr(l), uld(l), LevelPtr<T>::f(c->levels[l + 1]), width, lv.nx, c->opt.nu1, ntx, (int)p1);
         }
         if (int rc = coarse_part()) return rc;
         for (int l = Ltop - 1; l >= 0; --l) {
@@ -1965,9 +1991,8 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             const int nb = tiles(lv, ntx);
             const T* ec = l + 1 == Ltop ? uptr(Ltop) : LevelPtr<T>::u2(c->levels[l + 1]);
             T* out = l == 0 ? u0 : LevelPtr<T>::u2(lv);
-            hipLaunchKernelGGL(k_cycle1_up<T>, dim3(nb), dim3(1024), 0, c->stream, LevelPtr<T>::stp(lv), fptr(l),
-                               fld(l), (const T*)uptr(l), uld(l), ec, 1, out, l == 0 ? ldu0 : 1, lv.nx, c->opt.nu2,
-                               ntx, (int)p1);
+            launch_tile<T>(false, width, nb, c->stream, LevelPtr<T>::stp(lv), fptr(l), fld(l), uptr(l), uld(l), ec,
+                           width, out, l == 0 ? ldu0 : width, nullptr, 0, lv.nx, c->opt.nu2, ntx, (int)p1);
         }
         return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
     }

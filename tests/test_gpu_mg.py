@@ -27,6 +27,8 @@ pytestmark = pytest.mark.gpu
     (128, 6, "four", (2, 2), 8, False),      # narrow row-phase smoother (lanes over rows and modes)
     (256, 21, "four", (1, 2), 8, True),
     (256, 1, "four", (2, 2), 8, False),
+    (128, 8, "four", (2, 1), 8, True),       # tile cycle of a few modes (float), uneven sweep counts
+    (256, 3, "four", (1, 2), 8, False),
 ])
 def test_vcycle_matches_oracle(n, width, colour, nu, coarsest, a0):
     import paper_1304_1755_amd as sgbt
