@@ -1876,7 +1876,9 @@ bool use_row_sweeps(const sg_ctx* c, int width) {
 
 // block widths the tile cycle takes: a workgroup per (tile, mode), so the
 // launch holds width times the tiles; wider blocks keep the row-phase kernels
-constexpr int kTileMaxWidth = 8;
+constexpr int kTileMaxWidth = 8;   // every level
+constexpr int kTileMidWidth = 32;  // on grids of at most kTileMidNx nodes per side
+constexpr int kTileMidNx = 127;
 
 template <typename T>
 void launch_tile(bool down, int width, int ntiles, hipStream_t st, const T* stp, const T* f, int ldf, const T* ui,
@@ -1967,36 +1969,26 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
         }
         return SG_OK;
     };
-    if (width <= kTileMaxWidth && c->opt.colour_mode == SG_COLOUR_FOUR && c->opt.nu1 <= kTileMaxNu &&
-        c->opt.nu2 <= kTileMaxNu && Ltop > 0) {
-        // a few modes: two tile launches per level above the coarse part; the
-        // smoothed values of level l go to uptr(l), the corrected ones to the
-        // level's second buffer (u0 on the finest level)
-        auto tiles = [&](const Level& lv, int& ntx) {
-            const int nxc = (lv.nx - 1) / 2;
-            ntx = (nxc + kTileCX - 1) / kTileCX;
-            return ntx * ((nxc + kTileCY - 1) / kTileCY);
-        };
-        for (int l = 0; l < Ltop; ++l) {
-            Level& lv = c->levels[l];
-            int ntx;
-            const int nb = tiles(lv, ntx);
-            launch_tile<T>(true, width, nb, c->stream, LevelPtr<T>::stp(lv), fptr(l), fld(l), nullptr, 0, nullptr, 0,
-                           uptr(l), uld(l), LevelPtr<T>::f(c->levels[l + 1]), width, lv.nx, c->opt.nu1, ntx, (int)p1);
-        }
-        if (int rc = coarse_part()) return rc;
-        for (int l = Ltop - 1; l >= 0; --l) {
-            Level& lv = c->levels[l];
-            int ntx;
-            const int nb = tiles(lv, ntx);
-            const T* ec = l + 1 == Ltop ? uptr(Ltop) : LevelPtr<T>::u2(c->levels[l + 1]);
-            T* out = l == 0 ? u0 : LevelPtr<T>::u2(lv);
-            launch_tile<T>(false, width, nb, c->stream, LevelPtr<T>::stp(lv), fptr(l), fld(l), uptr(l), uld(l), ec,
-                           width, out, l == 0 ? ldu0 : width, nullptr, 0, lv.nx, c->opt.nu2, ntx, (int)p1);
-        }
-        return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
-    }
-    for (int l = 0; l < Ltop; ++l) {
+    // Levels lt .. Ltop-1 are cycled by tiles (two launches per level): every
+    // level for blocks of at most kTileMaxWidth modes, grids of at most
+    // kTileMidNx nodes per side for blocks of at most kTileMidWidth modes.  A
+    // tile level keeps its smoothed values in uptr(l) and writes its corrected
+    // ones to the level's second buffer (u0 on the finest level).
+    int lt = Ltop;
+    if (c->opt.colour_mode == SG_COLOUR_FOUR && c->opt.nu1 <= kTileMaxNu && c->opt.nu2 <= kTileMaxNu)
+        for (int l = 0; l < Ltop; ++l)
+            if (width <= kTileMaxWidth || (width <= kTileMidWidth && c->levels[l].nx <= kTileMidNx)) {
+                lt = l;
+                break;
+            }
+    // the corrected values of level l, which the prolongation of level l - 1 reads
+    auto sol = [&](int l) -> const T* { return l >= lt && l < Ltop ? LevelPtr<T>::u2(c->levels[l]) : uptr(l); };
+    auto tiles = [&](const Level& lv, int& ntx) {
+        const int nxc = (lv.nx - 1) / 2;
+        ntx = (nxc + kTileCX - 1) / kTileCX;
+        return ntx * ((nxc + kTileCY - 1) / kTileCY);
+    };
+    for (int l = 0; l < lt; ++l) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
         // zero initial guess: the first sweep skips not-yet-updated neighbours, so u needs no clearing
@@ -2029,8 +2021,23 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
                                (const T*)r, width, LevelPtr<T>::f(lc), width, lc.nx, width, (int)p1);
         }
     }
+    for (int l = lt; l < Ltop; ++l) {
+        Level& lv = c->levels[l];
+        int ntx;
+        const int nb = tiles(lv, ntx);
+        launch_tile<T>(true, width, nb, c->stream, LevelPtr<T>::stp(lv), fptr(l), fld(l), nullptr, 0, nullptr, 0,
+                       uptr(l), uld(l), LevelPtr<T>::f(c->levels[l + 1]), width, lv.nx, c->opt.nu1, ntx, (int)p1);
+    }
     if (int rc = coarse_part()) return rc;
-    for (int l = Ltop - 1; l >= 0; --l) {
+    for (int l = Ltop - 1; l >= lt; --l) {
+        Level& lv = c->levels[l];
+        int ntx;
+        const int nb = tiles(lv, ntx);
+        T* out = l == 0 ? u0 : LevelPtr<T>::u2(lv);
+        launch_tile<T>(false, width, nb, c->stream, LevelPtr<T>::stp(lv), fptr(l), fld(l), uptr(l), uld(l), sol(l + 1),
+                       width, out, l == 0 ? ldu0 : width, nullptr, 0, lv.nx, c->opt.nu2, ntx, (int)p1);
+    }
+    for (int l = lt - 1; l >= 0; --l) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
         if (width >= kWalkMinWidth) {
@@ -2041,14 +2048,14 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
             auto pr = shortw ? (p1 ? k_prolong_rows<T, kPrSegShort, true> : k_prolong_rows<T, kPrSegShort, false>)
                              : (p1 ? k_prolong_rows<T, kPrSeg, true> : k_prolong_rows<T, kPrSeg, false>);
             hipLaunchKernelGGL(pr, dim3(lv.nx * nseg),
-                               dim3(64 * nws), 0, c->stream, (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u,
+                               dim3(64 * nws), 0, c->stream, sol(l + 1), width, u,
                                uld(l), lv.nx, width, nseg);
         } else if (tl.tx == 64)
             hipLaunchKernelGGL((k_prolong_add<T, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width, (int)p1);
+                               sol(l + 1), width, u, uld(l), lv.nx, width, (int)p1);
         else
             hipLaunchKernelGGL((k_prolong_add<T, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
-                               (const T*)LevelPtr<T>::u(c->levels[l + 1]), width, u, uld(l), lv.nx, width, (int)p1);
+                               sol(l + 1), width, u, uld(l), lv.nx, width, (int)p1);
         if (use_row_sweeps<T>(c, width))
             row_sweeps<T>(c, l, u, uld(l), fptr(l), fld(l), width, true, c->opt.nu2, false, l == 0 ? u0 : nullptr,
                           l == 0 ? ldu0 : 0);
