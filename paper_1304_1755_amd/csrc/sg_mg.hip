@@ -25,7 +25,7 @@
 //   * four-colour smoothing runs as row phases (one launch per row parity,
 //     both colours of a row): for W >= 32 a workgroup walks a row segment
 //     with lanes over modes (k_gs_rows; the first sweep from the zero start
-//     takes both phases in one launch, k_gs_sweep); narrower blocks give each
+//     takes both phases in one launch, k_gs_sweep0); narrower blocks give each
 //     lane one (row, S node, mode) triple (k_gs_rows_narrow);
 //   * for W >= 16 residual + restriction is one walking pass
 //     (k_resid_restrict) and the prolongation another (k_prolong_rows);
@@ -534,12 +534,12 @@ constexpr int kRowSegShort = 8;   // on coarse levels, where long walks leave to
 template <typename T>
 constexpr int gs_ring() { return sizeof(T) == 4 ? 4 : 3; }
 
-template <typename T, bool OWNZ, int SEG>
+template <typename T, int SEG>
 __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, const T* __restrict__ rdiag,
                                                  const T* __restrict__ A, int lda,
                                                  const T* __restrict__ V, int ldv, const T* __restrict__ f, int ldf,
                                                  T* __restrict__ B, int ldb, int nx, int width, int py, int fx,
-                                                 int vert_zero, int nseg, int nrows) {
+                                                 int nseg, int nrows) {
     constexpr int NIT = SEG / 2;          // S nodes per segment
     constexpr int D = gs_ring<T>();
     constexpr int SP = sizeof(T) == 4 ? 12 : 10;  // LDS pitch of a staged stencil
@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     const int y = py + 2 * r;
     const int x0 = (lb - r * nseg) * SEG;  // even
     const int x1 = min(x0 + SEG, nx);
-    const bool has_dn = y > 0 && !vert_zero, has_up = y + 1 < nx && !vert_zero;
+    const bool has_dn = y > 0, has_up = y + 1 < nx;
     const int ydn = y > 0 ? y - 1 : y, yup = y + 1 < nx ? y + 1 : y;
     // stencils of columns x0-1 .. x0+SEG (clamped), column c at stl[c * SP], the reciprocal
     // of its diagonal at stl[c * SP + 9]
@@ -573,11 +573,11 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     const T* const dnrow = V + (size_t)ydn * nx * ldv;
     const T* const uprow = V + (size_t)yup * nx * ldv;
     T* const brow = B + (size_t)y * nx * ldb;
-    auto gA = [&](int x) -> T { return OWNZ ? T(0) : (arow + cx(x) * lda)[tc]; };
+    auto gA = [&](int x) -> T { return (arow + cx(x) * lda)[tc]; };
     auto gD = [&](int x) -> T { return (dnrow + cx(x) * ldv)[tc]; };
     auto gU = [&](int x) -> T { return (uprow + cx(x) * ldv)[tc]; };
     auto gf = [&](int x) -> T { return (frow + cx(x) * ldf)[tc]; };
-    auto zA = [&](T v, int x) -> T { return (!OWNZ && inx(x)) ? v : T(0); };
+    auto zA = [&](T v, int x) -> T { return inx(x) ? v : T(0); };
     auto zD = [&](T v, int x) -> T { return (has_dn && inx(x)) ? v : T(0); };
     auto zU = [&](T v, int x) -> T { return (has_up && inx(x)) ? v : T(0); };
     // new value at column x from its same-row neighbours wl, wr and the rows
@@ -648,32 +648,30 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     }
 }
 
-// One whole four-colour sweep by row phases in one launch (W >= 32 modes).
-// A workgroup owns a segment of one phase-1 row y1 (parity p1) and walks it
-// together with the two phase-0 rows y1 - 1 and y1 + 1 around it: each step
-// relaxes the phase-0 rows at S node s0 and F node s0 + 1 from the old values
-// (rows y1 - 2 .. y1 + 2), then the phase-1 row one step behind, at s0 - 2 and
-// s0 - 1, from the new values of the phase-0 rows kept in registers.  The
-// phase-0 rows are relaxed twice (by the workgroups of y1 and y1 + 2; row 0
-// by the one of y1 = 1) and written once, by the workgroup below them; their
-// walk starts two S nodes left of the segment and ends one right of it so
-// that the phase-1 row has all its new neighbours.  Every node gets exactly
-// the update of k_gs_rows (same formula, same inputs), so a sweep equals its
-// two row-phase launches.  It runs for the first sweep from the zero start
-// (OWNZ: no old values, only f is read), where it replaces two launches and
-// the re-read of the phase-0 rows; with old values to read, its longer step
-// (four relaxations, fourteen loads) ran no faster than the two row-phase
-// launches, which the other sweeps keep.
-template <typename T, bool OWNZ, int SEG>
-__global__ void __launch_bounds__(256) k_gs_sweep(const T* __restrict__ stp, const T* __restrict__ A, int lda,
-                                                  const T* __restrict__ f, int ldf, T* __restrict__ B, int ldb,
-                                                  int nx, int width, int p1, int fx, int nseg, int nrows1) {
+// The first four-colour sweep from the zero start, both row phases in one
+// launch (W >= 32 modes).  A workgroup owns a segment of one phase-1 row y1
+// (parity p1) and walks it together with the two phase-0 rows y1 - 1 and
+// y1 + 1 around it: each step relaxes the phase-0 rows at S node s0 and F
+// node s0 + 1 (from f alone: every old value is the zero start), then the
+// phase-1 row one step behind, at s0 - 2 and s0 - 1, from the new values of
+// the phase-0 rows kept in registers.  The phase-0 rows are relaxed twice (by
+// the workgroups of y1 and y1 + 2; row 0 by the one of y1 = 1) and written
+// once, by the workgroup below them; their walk starts two S nodes left of
+// the segment and ends one right of it so that the phase-1 row has all its
+// new neighbours.  Every node gets the update of k_gs_rows (same formula, the
+// old values as exact zeros), so the launch equals the two row-phase launches
+// of the sweep; only f is read.  (A form of this walk for sweeps with old
+// values ran no faster than their two row-phase launches.)
+template <typename T, int SEG>
+__global__ void __launch_bounds__(256) k_gs_sweep0(const T* __restrict__ stp, const T* __restrict__ f, int ldf,
+                                                   T* __restrict__ B, int ldb, int nx, int width, int p1, int fx,
+                                                   int nseg, int nrows1) {
     constexpr int NIT = SEG / 2;                   // phase-1 S nodes per segment
     constexpr int NJ = NIT + 2;                    // phase-0 steps
     constexpr int D = 2;                           // steps of loads in flight
     constexpr int SP = sizeof(T) == 4 ? 12 : 10;  // pitch of a padded stencil (9 + reciprocal diagonal)
     constexpr int NC = SEG + 8;                    // staged columns sf - 4 .. sf + SEG + 3
-    constexpr int NL = 14;                         // loads per step
+    constexpr int NL = 6;                          // loads per step
     __shared__ T stl[3 * NC * SP];
     const int lane = threadIdx.x & 63;
     const int s_w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -698,15 +696,7 @@ __global__ void __launch_bounds__(256) k_gs_sweep(const T* __restrict__ stp, con
     __syncthreads();
     const bool hasA = y1 >= 1, hasB = y1 + 1 < nx;  // phase-0 rows y1 - 1, y1 + 1
     const bool writeA = y1 == 1;                     // row 0 has no workgroup below it
-    // old rows y1 - 2 .. y1 + 2 (k = 0..4), f rows y1 - 1 .. y1 + 1, output rows y1 - 1 .. y1 + 1
-    bool rin[5];
-    const T* orow[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const int yy = y1 - 2 + k;
-        rin[k] = yy >= 0 && yy < nx;
-        orow[k] = A + (size_t)(rin[k] ? yy : 0) * nx * lda;
-    }
+    // f rows y1 - 1 .. y1 + 1 and output rows (clamped into the grid)
     const T* frow[3];
     T* brow[3];
 #pragma unroll
@@ -717,9 +707,8 @@ __global__ void __launch_bounds__(256) k_gs_sweep(const T* __restrict__ stp, con
     }
     auto cx = [&](int x) { return min(max(x, 0), nx - 1); };
     auto inx = [&](int x) { return x >= 0 && x < nx; };
-    auto gO = [&](int k, int x) -> T { return OWNZ ? T(0) : (orow[k] + cx(x) * lda)[tc]; };
-    auto zO = [&](T v, int k, int x) -> T { return (!OWNZ && rin[k] && inx(x)) ? v : T(0); };
     auto gF = [&](int k, int x) -> T { return (frow[k] + cx(x) * ldf)[tc]; };
+    const T z = T(0);  // an old value (the zero start)
     auto relax = [&](int rk, int x, T fv, T wl, T wr, T d0, T d1, T d2, T u0, T u1, T u2) -> T {
         const T* st = stl + (rk * NC + (x - cb)) * SP;
         T acc = fv;
@@ -731,53 +720,28 @@ __global__ void __launch_bounds__(256) k_gs_sweep(const T* __restrict__ stp, con
     auto put = [&](int rk, int x, T v) {
         if (ok && x >= x0 && x < x1) (brow[rk] + x * ldb)[t] = v;
     };
-    // loads of phase-0 step j (s0 = sf - 2 + 2j): old rows 0, 2, 4 at s0 + 1, s0 + 2; the old S
-    // nodes of rows 1, 3 at s0 + 2; f of rows y1 - 1, y1, y1 + 1 at s0, s0 + 1
+    // loads of phase-0 step j (s0 = sf - 2 + 2j): f of rows y1 - 1, y1, y1 + 1 at s0, s0 + 1
     T q[D][NL];
     auto issue = [&](int j, int slot) {
         const int s0 = sf - 2 + 2 * j;
-        q[slot][0] = gO(0, s0 + 1);
-        q[slot][1] = gO(0, s0 + 2);
-        q[slot][2] = gO(2, s0 + 1);
-        q[slot][3] = gO(2, s0 + 2);
-        q[slot][4] = gO(4, s0 + 1);
-        q[slot][5] = gO(4, s0 + 2);
-        q[slot][6] = gO(1, s0 + 2);
-        q[slot][7] = gO(3, s0 + 2);
-        q[slot][8] = gF(0, s0);
-        q[slot][9] = gF(0, s0 + 1);
-        q[slot][10] = gF(1, s0);
-        q[slot][11] = gF(1, s0 + 1);
-        q[slot][12] = gF(2, s0);
-        q[slot][13] = gF(2, s0 + 1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            q[slot][2 * k] = gF(k, s0);
+            q[slot][2 * k + 1] = gF(k, s0 + 1);
+        }
     };
-    // prologue values: old rows 0, 2, 4 at sf - 4 .. sf - 2, old S of rows 1, 3 at sf - 4, sf - 2,
-    // f of rows y1 -+ 1 at sf - 3
-    T w0[4], w2[4], w4[4];  // old rows 0, 2, 4 at s0 - 1 .. s0 + 2 (before a step: at s0 - 3 .. s0)
-    const T p0 = gO(0, sf - 4), p2 = gO(2, sf - 4), p4 = gO(4, sf - 4);
-    w0[2] = gO(0, sf - 3); w0[3] = gO(0, sf - 2);
-    w2[2] = gO(2, sf - 3); w2[3] = gO(2, sf - 2);
-    w4[2] = gO(4, sf - 3); w4[3] = gO(4, sf - 2);
-    T Sa0 = gO(1, sf - 2), Sb0 = gO(3, sf - 2);
-    const T Sam = gO(1, sf - 4), Sbm = gO(3, sf - 4);
     const T fa3 = gF(0, sf - 3), fb3 = gF(2, sf - 3);
 #pragma unroll
     for (int k = 0; k < D; ++k) issue(k, k);
-    w0[2] = zO(w0[2], 0, sf - 3); w0[3] = zO(w0[3], 0, sf - 2);
-    w2[2] = zO(w2[2], 2, sf - 3); w2[3] = zO(w2[3], 2, sf - 2);
-    w4[2] = zO(w4[2], 4, sf - 3); w4[3] = zO(w4[3], 4, sf - 2);
-    Sa0 = zO(Sa0, 1, sf - 2);
-    Sb0 = zO(Sb0, 3, sf - 2);
     // new F(sf - 3) of the phase-0 rows
-    T FaPrev = T(0), FbPrev = T(0);
+    T FaPrev = z, FbPrev = z;
     if (inx(sf - 3)) {
-        const T d0 = zO(p0, 0, sf - 4), d2 = zO(p2, 2, sf - 4), d4 = zO(p4, 4, sf - 4);
-        if (hasA) FaPrev = relax(0, sf - 3, fa3, zO(Sam, 1, sf - 4), Sa0, d0, w0[2], w0[3], d2, w2[2], w2[3]);
-        if (hasB) FbPrev = relax(2, sf - 3, fb3, zO(Sbm, 3, sf - 4), Sb0, d2, w2[2], w2[3], d4, w4[2], w4[3]);
+        if (hasA) FaPrev = relax(0, sf - 3, fa3, z, z, z, z, z, z, z, z);
+        if (hasB) FbPrev = relax(2, sf - 3, fb3, z, z, z, z, z, z, z, z);
     }
     // new values of the phase-0 rows at s0 - 3 .. s0 + 1 (after a step)
-    T nA[5] = {T(0), T(0), T(0), T(0), FaPrev}, nB[5] = {T(0), T(0), T(0), T(0), FbPrev};
-    T s1p = T(0), f1p0 = T(0), f1p1 = T(0), F1prev = T(0);
+    T nA[5] = {z, z, z, z, FaPrev}, nB[5] = {z, z, z, z, FbPrev};
+    T f1p0 = z, f1p1 = z, F1prev = z;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const int k = j % D;
@@ -786,24 +750,19 @@ __global__ void __launch_bounds__(256) k_gs_sweep(const T* __restrict__ stp, con
 #pragma unroll
         for (int e = 0; e < NL; ++e) v[e] = q[k][e];
         if (j + D < NJ) issue(j + D, k);
-        // windows move two columns
-        w0[0] = w0[2]; w0[1] = w0[3]; w0[2] = zO(v[0], 0, s0 + 1); w0[3] = zO(v[1], 0, s0 + 2);
-        w2[0] = w2[2]; w2[1] = w2[3]; w2[2] = zO(v[2], 2, s0 + 1); w2[3] = zO(v[3], 2, s0 + 2);
-        w4[0] = w4[2]; w4[1] = w4[3]; w4[2] = zO(v[4], 4, s0 + 1); w4[3] = zO(v[5], 4, s0 + 2);
-        const T Sa2 = zO(v[6], 1, s0 + 2), Sb2 = zO(v[7], 3, s0 + 2);
         // phase 0: F(s0 + 1) from the old S(s0), S(s0 + 2); then S(s0) from the new F(s0 - 1), F(s0 + 1)
-        T Fa = T(0), Sa = T(0), Fb = T(0), Sb = T(0);
+        T Fa = z, Sa = z, Fb = z, Sb = z;
         if (hasA) {
-            if (inx(s0 + 1)) Fa = relax(0, s0 + 1, v[9], Sa0, Sa2, w0[1], w0[2], w0[3], w2[1], w2[2], w2[3]);
-            if (inx(s0)) Sa = relax(0, s0, v[8], FaPrev, Fa, w0[0], w0[1], w0[2], w2[0], w2[1], w2[2]);
+            if (inx(s0 + 1)) Fa = relax(0, s0 + 1, v[1], z, z, z, z, z, z, z, z);
+            if (inx(s0)) Sa = relax(0, s0, v[0], FaPrev, Fa, z, z, z, z, z, z);
             if (writeA) {
                 put(0, s0 + 1, Fa);
                 put(0, s0, Sa);
             }
         }
         if (hasB) {
-            if (inx(s0 + 1)) Fb = relax(2, s0 + 1, v[13], Sb0, Sb2, w2[1], w2[2], w2[3], w4[1], w4[2], w4[3]);
-            if (inx(s0)) Sb = relax(2, s0, v[12], FbPrev, Fb, w2[0], w2[1], w2[2], w4[0], w4[1], w4[2]);
+            if (inx(s0 + 1)) Fb = relax(2, s0 + 1, v[5], z, z, z, z, z, z, z, z);
+            if (inx(s0)) Sb = relax(2, s0, v[4], FbPrev, Fb, z, z, z, z, z, z);
             put(2, s0 + 1, Fb);
             put(2, s0, Sb);
         }
@@ -813,24 +772,21 @@ __global__ void __launch_bounds__(256) k_gs_sweep(const T* __restrict__ stp, con
         if (j == 1) {
             // new F(sf - 1) from the old S(sf - 2), S(sf)
             if (inx(sf - 1)) {
-                F1prev = relax(1, sf - 1, f1p1, s1p, w2[1], nA[1], nA[2], nA[3], nB[1], nB[2], nB[3]);
+                F1prev = relax(1, sf - 1, f1p1, z, z, nA[1], nA[2], nA[3], nB[1], nB[2], nB[3]);
                 put(1, sf - 1, F1prev);
             }
         } else if (j >= 2) {
             const int s = s0 - 2;
-            T F1 = T(0);
+            T F1 = z;
             if (inx(s + 1)) {
-                F1 = relax(1, s + 1, f1p1, s1p, w2[1], nA[1], nA[2], nA[3], nB[1], nB[2], nB[3]);
+                F1 = relax(1, s + 1, f1p1, z, z, nA[1], nA[2], nA[3], nB[1], nB[2], nB[3]);
                 put(1, s + 1, F1);
             }
             if (inx(s)) put(1, s, relax(1, s, f1p0, F1prev, F1, nA[0], nA[1], nA[2], nB[0], nB[1], nB[2]));
             F1prev = F1;
         }
-        s1p = w2[1];  // old S(s0) of row y1
-        f1p0 = v[10];
-        f1p1 = v[11];
-        Sa0 = Sa2;
-        Sb0 = Sb2;
+        f1p0 = v[2];
+        f1p1 = v[3];
         FaPrev = Fa;
         FbPrev = Fb;
     }
@@ -1820,20 +1776,19 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
             const int p1 = 1 - py1;
             const int nrows1 = (nx - p1 + 1) / 2;
             auto go = [&](auto kern) {
-                hipLaunchKernelGGL(kern, dim3(nrows1 * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::stp(lv),
-                                   (const T*)src, lds, f, ldf, dst, ldd, nx, width, p1, fx, nseg, nrows1);
+                hipLaunchKernelGGL(kern, dim3(nrows1 * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::stp(lv), f,
+                                   ldf, dst, ldd, nx, width, p1, fx, nseg, nrows1);
             };
-            shortw ? go(k_gs_sweep<T, true, kRowSegShort>) : go(k_gs_sweep<T, true, kRowSeg>);
+            shortw ? go(k_gs_sweep0<T, kRowSegShort>) : go(k_gs_sweep0<T, kRowSeg>);
         } else if (width >= 32) {
             for (int ph = 0; ph < 2; ++ph) {
                 const int py = ph == 0 ? py1 : 1 - py1;
                 const int nrows = (nx - py + 1) / 2;
                 const T* vsrc = ph == 0 ? src : dst;
                 const int ldv = ph == 0 ? lds : ldd;
-                hipLaunchKernelGGL((shortw ? k_gs_rows<T, false, kRowSegShort> : k_gs_rows<T, false, kRowSeg>),
-                                   dim3(nrows * nseg), dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv),
-                                   LevelPtr<T>::rd(lv), (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py,
-                                   fx, 0, nseg, nrows);
+                hipLaunchKernelGGL((shortw ? k_gs_rows<T, kRowSegShort> : k_gs_rows<T, kRowSeg>), dim3(nrows * nseg),
+                                   dim3(64 * nws), 0, c->stream, LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv),
+                                   (const T*)src, lds, vsrc, ldv, f, ldf, dst, ldd, nx, width, py, fx, nseg, nrows);
             }
         } else {
             for (int ph = 0; ph < 2; ++ph) {
