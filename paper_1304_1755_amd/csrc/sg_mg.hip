@@ -985,22 +985,23 @@ __global__ void __launch_bounds__(1024) k_cycle1_up(const T* __restrict__ stp, c
 // Row-phase Gauss-Seidel for narrow blocks (W <= 32 modes): the same update
 // as k_gs_rows without the walk.  A lane owns, for one mode, the S node s of
 // a row and the F node s + 1, and recomputes the F node s - 1 that its S
-// update also needs; lanes cover (row, S node, mode) with Wp = W rounded up
-// to a power of two lanes per node, so narrow blocks still fill the chip and
-// every lane issues all its loads at once.  Addresses are clamped into the
+// update also needs; lanes cover (row, S node, mode), wpad >= W adjacent
+// lanes per node pair, so narrow blocks still fill the chip and every lane
+// issues all its loads at once.  Addresses are clamped into the
 // grid and values outside it replaced by zero.
 template <typename T, bool OWNZ>
 __global__ void __launch_bounds__(256) k_gs_rows_narrow(const T* __restrict__ stp,
                                                         const T* __restrict__ A, int lda,
                                                         const T* __restrict__ V, int ldv, const T* __restrict__ f,
                                                         int ldf, T* __restrict__ B, int ldb, int nx, int width,
-                                                        int wp_log2, int py, int fx, int vert_zero, int npairs,
+                                                        int wpad, int py, int fx, int vert_zero, int npairs,
                                                         int nrows) {
-    const int mode = threadIdx.x & ((1 << wp_log2) - 1);
-    const long gl = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const long pl = gl >> wp_log2;
-    const int r = (int)(pl / npairs);
-    const int j = (int)(pl - (long)r * npairs);
+    // lanes (pair, mode): wpad >= W adjacent lanes per node pair
+    const unsigned gl = (unsigned)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const unsigned pl = gl / (unsigned)wpad;
+    const int mode = (int)(gl - pl * (unsigned)wpad);
+    const int r = (int)(pl / (unsigned)npairs);
+    const int j = (int)(pl - (unsigned)r * (unsigned)npairs);
     if (r >= nrows || mode >= width) return;  // no barriers below
     const int y = py + 2 * r;
     // S nodes have parity 1 - fx; with fx = 0 the first pair is (none, F(0))
@@ -1797,19 +1798,22 @@ void row_sweeps(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width,
                 const T* vsrc = ph == 0 ? src : dst;
                 const int ldv = ph == 0 ? lds : ldd;
                 const int vzero = (ph == 0 && own_zero) ? 1 : 0;
-                int wl = 0;
-                while ((1 << wl) < width) ++wl;
                 const int npairs = fx ? (nx - 1) / 2 + 1 : nx / 2 + 1;  // pairs (S(s), F(s+1)) covering the row
-                const long lanes = (long)nrows * npairs << wl;
+                // lanes per pair: W rounded up to a power of two in float, W itself in double
+                // (measured faster each way at 21 modes)
+                int wpad = width;
+                if (sizeof(T) == 4)
+                    for (wpad = 1; wpad < width;) wpad <<= 1;
+                const long lanes = (long)nrows * npairs * wpad;
                 const int nblk = (int)((lanes + 255) / 256);
                 if (own_zero)
                     hipLaunchKernelGGL((k_gs_rows_narrow<T, true>), dim3(nblk), dim3(256), 0, c->stream,
                                        LevelPtr<T>::stp(lv), (const T*)src, lds, vsrc, ldv, f, ldf,
-                                       dst, ldd, nx, width, wl, py, fx, vzero, npairs, nrows);
+                                       dst, ldd, nx, width, wpad, py, fx, vzero, npairs, nrows);
                 else
                     hipLaunchKernelGGL((k_gs_rows_narrow<T, false>), dim3(nblk), dim3(256), 0, c->stream,
                                        LevelPtr<T>::stp(lv), (const T*)src, lds, vsrc, ldv, f, ldf,
-                                       dst, ldd, nx, width, wl, py, fx, vzero, npairs, nrows);
+                                       dst, ldd, nx, width, wpad, py, fx, vzero, npairs, nrows);
             }
         }
         std::swap(src, dst);
