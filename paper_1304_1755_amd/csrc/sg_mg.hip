@@ -1835,7 +1835,8 @@ bool use_row_sweeps(const sg_ctx* c, int width) {
 
 // block widths the tile cycle takes: a workgroup per (tile, mode), so the
 // launch holds width times the tiles; wider blocks keep the row-phase kernels
-constexpr int kTileMaxWidth = 8;   // every level
+constexpr int kTileMaxWidth = 8;   // every level with at most kTileMaxWorkgroups (tile, mode) pairs
+constexpr int kTileMaxWorkgroups = 1024;  // two rounds of the chip: each workgroup is latency-bound
 constexpr int kTileMidWidth = 32;  // on grids of at most kTileMidNx nodes per side
 constexpr int kTileMidNx = 127;
 
@@ -1928,25 +1929,30 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
         }
         return SG_OK;
     };
-    // Levels lt .. Ltop-1 are cycled by tiles (two launches per level): every
-    // level for blocks of at most kTileMaxWidth modes, grids of at most
-    // kTileMidNx nodes per side for blocks of at most kTileMidWidth modes.  A
+    // Levels lt .. Ltop-1 are cycled by tiles (two launches per level): for
+    // blocks of at most kTileMaxWidth modes every level with at most
+    // kTileMaxWorkgroups (tile, mode) pairs, for blocks of at most kTileMidWidth
+    // modes the grids of at most kTileMidNx nodes per side.  A
     // tile level keeps its smoothed values in uptr(l) and writes its corrected
     // ones to the level's second buffer (u0 on the finest level).
-    int lt = Ltop;
-    if (c->opt.colour_mode == SG_COLOUR_FOUR && c->opt.nu1 <= kTileMaxNu && c->opt.nu2 <= kTileMaxNu)
-        for (int l = 0; l < Ltop; ++l)
-            if (width <= kTileMaxWidth || (width <= kTileMidWidth && c->levels[l].nx <= kTileMidNx)) {
-                lt = l;
-                break;
-            }
-    // the corrected values of level l, which the prolongation of level l - 1 reads
-    auto sol = [&](int l) -> const T* { return l >= lt && l < Ltop ? LevelPtr<T>::u2(c->levels[l]) : uptr(l); };
     auto tiles = [&](const Level& lv, int& ntx) {
         const int nxc = (lv.nx - 1) / 2;
         ntx = (nxc + kTileCX - 1) / kTileCX;
         return ntx * ((nxc + kTileCY - 1) / kTileCY);
     };
+    int lt = Ltop;
+    if (c->opt.colour_mode == SG_COLOUR_FOUR && c->opt.nu1 <= kTileMaxNu && c->opt.nu2 <= kTileMaxNu)
+        for (int l = 0; l < Ltop; ++l) {
+            int ntx;
+            const long wgs = (long)tiles(c->levels[l], ntx) * width;
+            if ((width <= kTileMaxWidth && wgs <= kTileMaxWorkgroups) ||
+                (width <= kTileMidWidth && c->levels[l].nx <= kTileMidNx)) {
+                lt = l;
+                break;
+            }
+        }
+    // the corrected values of level l, which the prolongation of level l - 1 reads
+    auto sol = [&](int l) -> const T* { return l >= lt && l < Ltop ? LevelPtr<T>::u2(c->levels[l]) : uptr(l); };
     for (int l = 0; l < lt; ++l) {
         Level& lv = c->levels[l];
         T* u = uptr(l);
