@@ -293,34 +293,51 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
     auto Vj = [&](int j) { return c->ws.V + (size_t)j * vs; };
     auto Zj = [&](int j) { return (void*)((char*)c->ws.Z + (size_t)j * vs * zes); };
 
-    SG_HIP_CHECK(vec_dot(c->stream, F, F, np, c->ws.partial, scal));
-    if ((rc = fetch(c, scal, 1))) return rc;
-    const double nF = std::sqrt(hs[0]);
-    if (!(nF > 0.0) || !std::isfinite(nF)) {
+    // Without x0 the iterate stays zero until the first solution update, and
+    // every return before that update writes the zeros.
+    struct ZeroX {
+        hipStream_t s;
+        double* X;
+        int np;
+        bool pending;
+        ~ZeroX() {
+            if (pending) (void)launch_fill(s, X, 0, 1, np, 1);
+        }
+    } xz{c->stream, X, (int)np, !o.use_x0};
+    // From X = 0 the first candidate is F itself: when F is 16-byte aligned the
+    // first step reads it in place, and |F| comes from that step's dot products.
+    bool u_is_F = !o.use_x0 && (uintptr_t)F % 16 == 0;
+    double nF = 0.0, beta = 0.0;
+    if (!u_is_F) {
+        SG_HIP_CHECK(vec_dot(c->stream, F, F, np, c->ws.partial, scal));
+        if ((rc = fetch(c, scal, 1))) return rc;
+        nF = std::sqrt(hs[0]);
+        if (!std::isfinite(nF)) {
+            set_error("right-hand side norm is not finite");
+            return SG_ENAN;
+        }
         if (nF == 0.0) {
             info.rel_res_true = 0.0;
-            return launch_fill(c->stream, X, 0, 1, (int)np, 1);
+            xz.pending = true;
+            return SG_OK;
         }
-        set_error("right-hand side norm is not finite");
-        return SG_ENAN;
+        // r = F - A X, kept unnormalized as the first candidate V_0
+        beta = nF;
+        if (o.use_x0) {
+            if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+            SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
+            if ((rc = fetch(c, scal, 1))) return rc;
+            beta = std::sqrt(hs[0]);
+        } else {
+            SG_HIP_CHECK(hipMemcpyAsync(Vj(0), F, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        }
+        info.rel_res_true = beta / nF;
+        if (!std::isfinite(beta)) {
+            set_error("initial residual is not finite");
+            return SG_ENAN;
+        }
+        if (beta / nF < o.rtol) return SG_OK;
     }
-    if (!o.use_x0 && (rc = launch_fill(c->stream, X, 0, 1, (int)np, 1))) return rc;
-    // r = F - A X, kept unnormalized as the first candidate V_0 (r = F when X starts at zero)
-    double beta = nF;
-    if (o.use_x0) {
-        if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
-        SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
-        if ((rc = fetch(c, scal, 1))) return rc;
-        beta = std::sqrt(hs[0]);
-    } else {
-        SG_HIP_CHECK(hipMemcpyAsync(Vj(0), F, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    }
-    info.rel_res_true = beta / nF;
-    if (!std::isfinite(beta)) {
-        set_error("initial residual is not finite");
-        return SG_ENAN;
-    }
-    if (beta / nF < o.rtol) return SG_OK;
 
     const int ld = restart;
     // Hc: corrected Hessenberg matrix; Hr: columns as rotated for the running estimate
@@ -335,15 +352,16 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
         g[0] = beta;
         int k = 0;  // columns of this cycle
         for (int j = 0; j < restart; ++j) {
+            const double* uj = u_is_F ? F : Vj(j);
             tm.rec(0, c->stream);
-            if ((rc = apply_precond(c, o.precond, Vj(j), Zj(j), zf))) return rc;
+            if ((rc = apply_precond(c, o.precond, uj, Zj(j), zf))) return rc;
             tm.rec(1, c->stream);
             tm.rec(2, c->stream);
             if ((rc = launch_apply(c, c->plan_full, Zj(j), zf, nullptr, c->ws.w, 0, c->hs.P, c->hs.P, c->hs.P)))
                 return rc;
             tm.rec(3, c->stream);
             tm.rec(4, c->stream);
-            SG_HIP_CHECK(vec_dots2(c->stream, c->ws.V, vs, j, Vj(j), c->ws.w, np, c->ws.partial, scal));
+            SG_HIP_CHECK(vec_dots2(c->stream, c->ws.V, vs, j, uj, c->ws.w, np, c->ws.partial, scal));
             const int nch = j == 0 ? 1 : (j + kDc - 1) / kDc;
             if ((rc = fetch(c, scal, nch * kDcLd))) return rc;
             for (int i = 0; i < j; ++i) {
@@ -351,6 +369,16 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
                 b[i] = hs[(i / kDc) * kDcLd + kDc + (i % kDc)];
             }
             const double uu = hs[2 * kDc], uw = hs[2 * kDc + 1];
+            if (u_is_F) {  // first step from X = 0: u = F, beta = |F|
+                nF = beta = std::sqrt(uu);
+                if (!std::isfinite(nF)) {
+                    set_error("right-hand side norm is not finite");
+                    return SG_ENAN;
+                }
+                info.rel_res_true = nF == 0.0 ? 0.0 : 1.0;
+                if (nF == 0.0 || 1.0 < o.rtol) return SG_OK;
+                g[0] = beta;
+            }
             double nu2 = uu, ab = 0.0;
             for (int i = 0; i < j; ++i) {
                 nu2 -= a[i] * a[i];
@@ -378,8 +406,9 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
             }
             HC(j, j) = hjj;
             // q_j = (u - Q a) / nu into V_j;  w' = w - Q b - hjj q_j into V_{j+1}
-            SG_HIP_CHECK(vec_update2(c->stream, c->ws.V, vs, j, a.data(), cc.data(), 1.0 / nu, hjj / nu, Vj(j),
+            SG_HIP_CHECK(vec_update2(c->stream, c->ws.V, vs, j, a.data(), cc.data(), 1.0 / nu, hjj / nu, uj, Vj(j),
                                      c->ws.w, Vj(j + 1), np, c->ws.partial, scal + 256));
+            u_is_F = false;
             tm.rec(5, c->stream);
             if ((rc = fetch(c, scal + 256, 1))) return rc;
             tm.collect(true, true, true);
@@ -437,7 +466,8 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
         }
         std::memcpy(hs + 512, y.data(), k * sizeof(double));
         SG_HIP_CHECK(hipMemcpyAsync(scal + 512, hs + 512, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        SG_HIP_CHECK(vec_combine(c->stream, c->ws.Z, zf, vs, k, scal + 512, X, np));
+        SG_HIP_CHECK(vec_combine(c->stream, c->ws.Z, zf, vs, k, scal + 512, X, np, !xz.pending));
+        xz.pending = false;
         if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
         SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
         if ((rc = fetch(c, scal, 1))) return rc;

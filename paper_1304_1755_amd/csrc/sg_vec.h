@@ -25,15 +25,16 @@ struct DcCoef {
 // out[34 ch + 32] = u . u, out[34 ch + 33] = u . w  (ch = 0 .. ceil(nv / 16) - 1).
 hipError_t vec_dots2(hipStream_t s, const double* Q, size_t stride, int nv, const double* u, const double* w,
                      size_t len, double* partial, double* out);
-// vec_update2: u <- alpha u - sum_i a[i] Q_i, wout <- w - gamma u_old - sum_i c[i] Q_i (host a, c),
-// out_sq = |wout|^2 when partial_sq and out_sq are given.
+// vec_update2: u <- alpha uin - sum_i a[i] Q_i, wout <- w - gamma uin - sum_i c[i] Q_i (host a, c),
+// out_sq = |wout|^2 when partial_sq and out_sq are given; uin may be u (in place), else 16-byte aligned.
 hipError_t vec_update2(hipStream_t s, const double* Q, size_t stride, int nv, const double* a, const double* c,
-                       double alpha, double gamma, double* u, const double* w, double* wout, size_t len,
-                       double* partial_sq, double* out_sq);
+                       double alpha, double gamma, const double* uin, double* u, const double* w, double* wout,
+                       size_t len, double* partial_sq, double* out_sq);
 hipError_t vec_dot(hipStream_t s, const double* a, const double* b, size_t len, double* partial, double* out);
 hipError_t vec_scale(hipStream_t s, const double* src, double a, double* dst, size_t len);
+// x = (accumulate ? x : 0) + sum_i y[i] Z_i  (y on the device)
 hipError_t vec_combine(hipStream_t s, const void* Z, int z_float, size_t stride, int nz, const double* y, double* x,
-                       size_t len);
+                       size_t len, bool accumulate);
 hipError_t vec_axpy_sq(hipStream_t s, double a, const double* x, double* y, size_t len, double* partial,
                        double* out_sq);
 hipError_t vec_axpy(hipStream_t s, double a, const double* x, double* y, size_t len);

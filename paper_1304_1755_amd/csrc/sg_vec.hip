@@ -181,21 +181,27 @@ __global__ void k_scale(const double* __restrict__ src, double a, double* __rest
         dst[e] = a * src[e];
 }
 
-// x += sum_i y[i] Z_i  (Z float or double).  A thread owns pairs of
+// x = (acc ? x : 0) + sum_i y[i] Z_i  (Z float or double; x is not read
+// when acc is false).  A thread owns pairs of
 // consecutive entries and reads the Z_i four vectors at a time, all loads of a
 // group issued before its multiply-adds; the sum runs over i in order, as a
 // plain loop would.
 template <typename TZ>
 __global__ void __launch_bounds__(256) k_combine(const TZ* __restrict__ Z, size_t stride, int nz,
-                                                 const double* __restrict__ y, double* __restrict__ x, size_t len) {
+                                                 const double* __restrict__ y, double* __restrict__ x, size_t len,
+                                                 bool acc) {
     using TZ2 = typename std::conditional<sizeof(TZ) == 4, float2, double2>::type;
     __shared__ double ys[kMaxRestart];
     for (int i = threadIdx.x; i < nz; i += blockDim.x) ys[i] = y[i];
     __syncthreads();
     const size_t npair = len / 2;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < npair; e += (size_t)gridDim.x * blockDim.x) {
-        const double2 x0 = ((const double2*)x)[e];
-        double a0 = x0.x, a1 = x0.y;
+        double a0 = 0.0, a1 = 0.0;
+        if (acc) {
+            const double2 x0 = ((const double2*)x)[e];
+            a0 = x0.x;
+            a1 = x0.y;
+        }
         int i = 0;
         for (; i + 4 <= nz; i += 4) {
             TZ2 v[4];
@@ -217,9 +223,9 @@ __global__ void __launch_bounds__(256) k_combine(const TZ* __restrict__ Z, size_
     if (len & 1) {  // the last entry of an odd length
         const size_t e = len - 1;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            double acc = x[e];
-            for (int i = 0; i < nz; ++i) acc = fma(ys[i], (double)Z[(size_t)i * stride + e], acc);
-            x[e] = acc;
+            double t = acc ? x[e] : 0.0;
+            for (int i = 0; i < nz; ++i) t = fma(ys[i], (double)Z[(size_t)i * stride + e], t);
+            x[e] = t;
         }
     }
 }
@@ -228,14 +234,14 @@ __global__ void __launch_bounds__(256) k_combine(const TZ* __restrict__ Z, size_
 template <typename TZ>
 __global__ void __launch_bounds__(256) k_combine_scalar(const TZ* __restrict__ Z, size_t stride, int nz,
                                                         const double* __restrict__ y, double* __restrict__ x,
-                                                        size_t len) {
+                                                        size_t len, bool acc) {
     __shared__ double ys[kMaxRestart];
     for (int i = threadIdx.x; i < nz; i += blockDim.x) ys[i] = y[i];
     __syncthreads();
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
-        double acc = x[e];
-        for (int i = 0; i < nz; ++i) acc = fma(ys[i], (double)Z[(size_t)i * stride + e], acc);
-        x[e] = acc;
+        double t = acc ? x[e] : 0.0;
+        for (int i = 0; i < nz; ++i) t = fma(ys[i], (double)Z[(size_t)i * stride + e], t);
+        x[e] = t;
     }
 }
 
@@ -441,8 +447,8 @@ hipError_t vec_dots2(hipStream_t s, const double* Q, size_t stride, int nv, cons
     return hipGetLastError();
 }
 hipError_t vec_update2(hipStream_t s, const double* Q, size_t stride, int nv, const double* a, const double* c,
-                       double alpha, double gamma, double* u, const double* w, double* wout, size_t len,
-                       double* partial_sq, double* out_sq) {
+                       double alpha, double gamma, const double* uin, double* u, const double* w, double* wout,
+                       size_t len, double* partial_sq, double* out_sq) {
     if (stride & 1) return hipErrorInvalidValue;
     const int nch = nv == 0 ? 1 : (nv + kDc - 1) / kDc;
     for (int ch = 0; ch < nch; ++ch) {
@@ -452,18 +458,19 @@ hipError_t vec_update2(hipStream_t s, const double* Q, size_t stride, int nv, co
             cf.a[i] = a[c0 + i];
             cf.c[i] = c[c0 + i];
         }
-        // the first chunk scales u and takes gamma u from w; later chunks continue from the outputs
+        // the first chunk scales uin and takes gamma uin from w; later chunks continue from the outputs
         cf.alpha = ch == 0 ? alpha : 1.0;
         cf.gamma = ch == 0 ? gamma : 0.0;
         const double* win = ch == 0 ? w : wout;
+        const double* ui = ch == 0 ? uin : u;
         double* psq = ch == nch - 1 ? partial_sq : nullptr;
         const double* Qc = Q + (size_t)c0 * stride;
         if (cn <= 8)
-            hipLaunchKernelGGL(k_update2<8>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, cf, (const double*)u,
-                               win, u, wout, len, psq);
+            hipLaunchKernelGGL(k_update2<8>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, cf, ui, win, u, wout,
+                               len, psq);
         else
-            hipLaunchKernelGGL(k_update2<kDc>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, cf,
-                               (const double*)u, win, u, wout, len, psq);
+            hipLaunchKernelGGL(k_update2<kDc>, dim3(kRedBlocks), dim3(256), 0, s, Qc, stride, cn, cf, ui, win, u,
+                               wout, len, psq);
     }
     if (partial_sq && out_sq)
         hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial_sq, kRedBlocks, 1, 1, out_sq);
@@ -481,23 +488,23 @@ hipError_t vec_scale(hipStream_t s, const double* src, double a, double* dst, si
 }
 
 hipError_t vec_combine(hipStream_t s, const void* Z, int z_float, size_t stride, int nz, const double* y, double* x,
-                       size_t len) {
+                       size_t len, bool accumulate) {
     // pairs of entries need x 16-byte aligned and Z_i starting on an even entry (an even stride)
     const bool pairs = ((uintptr_t)x % 16 == 0) && ((uintptr_t)Z % 16 == 0) && stride % 2 == 0;
     if (z_float) {
         if (pairs)
             hipLaunchKernelGGL(k_combine<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)Z, stride, nz, y, x,
-                               len);
+                               len, accumulate);
         else
             hipLaunchKernelGGL(k_combine_scalar<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)Z, stride, nz,
-                               y, x, len);
+                               y, x, len, accumulate);
     } else {
         if (pairs)
             hipLaunchKernelGGL(k_combine<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)Z, stride, nz, y,
-                               x, len);
+                               x, len, accumulate);
         else
             hipLaunchKernelGGL(k_combine_scalar<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)Z, stride,
-                               nz, y, x, len);
+                               nz, y, x, len, accumulate);
     }
     return hipGetLastError();
 }

@@ -116,6 +116,55 @@ def test_restarts_initial_guess_and_errors():
     g.close()
 
 
+def test_solve_from_zero_writes_the_iterate():
+    # From X = 0 the solver reads F in place (16-byte aligned F) or copies it
+    # (8-byte aligned F); both give the same iterate, and every exit writes U.
+    import torch
+
+    import paper_1304_1755_amd as sgbt
+    note("solve from zero: aligned/unaligned F, zero F, NaN F")
+    g = sgbt.Problem(32, 3, 3, 0.3)
+    o = system.build_problem(32, 3, 3, 0.3)
+    A = system.assemble_A(o)
+    F = g.rhs()
+    buf = torch.empty(g.N * g.P + 1, dtype=torch.float64, device="cuda")
+    Fu = buf[1:].view(g.N, g.P)
+    Fu.copy_(F)
+    assert F.data_ptr() % 16 == 0 and Fu.data_ptr() % 16 == 8
+    res = []
+    for FF in (F, Fu):
+        for prec in (0, 2):
+            U = torch.full((g.N, g.P), float("nan"), dtype=torch.float64, device="cuda")
+            U, info = g.solve(F=FF, U=U, precond="tri", prec=prec, restart=20, rtol=1e-9)
+            Uh = to_host(U).T
+            assert info["status"] == 0 and np.isfinite(Uh).all()
+            assert np.linalg.norm(o.rhs().ravel() - A @ Uh.ravel()) / np.linalg.norm(o.rhs()) < 1e-9
+            res.append((info["iters"], Uh))
+    for prec in (0, 1):
+        assert res[prec][0] == res[2 + prec][0]
+        assert rel_max(res[prec][1], res[2 + prec][1]) < 1e-12
+    # a zero right-hand side: U = 0 at once, aligned or not
+    for FF in (torch.zeros_like(F), buf[1:].view(g.N, g.P).zero_()):
+        U = torch.full((g.N, g.P), float("nan"), dtype=torch.float64, device="cuda")
+        U, info = g.solve(F=FF, U=U, precond="tri")
+        assert info["status"] == 0 and info["iters"] == 0 and info["rel_res_true"] == 0.0
+        assert (to_host(U) == 0.0).all()
+    # a tolerance of at least 1 is met by X = 0
+    U = torch.full((g.N, g.P), float("nan"), dtype=torch.float64, device="cuda")
+    U, info = g.solve(F=F, U=U, precond="tri", rtol=2.0)
+    assert info["iters"] == 0 and (to_host(U) == 0.0).all()
+    # NaN in F: SG_ENAN, and U holds the zero iterate
+    Fn = F.clone()
+    Fn[5, 1] = float("nan")
+    for FF in (Fn, buf[1:].view(g.N, g.P).copy_(Fn)):
+        U = torch.full((g.N, g.P), float("nan"), dtype=torch.float64, device="cuda")
+        with pytest.raises(sgbt.SGError) as e:
+            g.solve(F=FF, U=U, precond="tri")
+        assert e.value.code == sgbt.SG_ENAN
+        assert (to_host(U) == 0.0).all()
+    g.close()
+
+
 @pytest.mark.parametrize("m,p,n", [(1, 4, 16), (3, 2, 32), (0, 0, 16)])
 def test_odd_sizes_and_degenerate_chaos(m, p, n):
     # N*P odd (P = 5, N = 225), a single mode (m = 0: the deterministic problem)
