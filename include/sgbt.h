@@ -91,11 +91,16 @@ typedef struct {
 } sg_options;
 
 typedef struct {
-    int solver;   /* 0: right-preconditioned FGMRES(restart); 1: PCG (precond 0 or 2);
+    int solver;   /* 0: right-preconditioned FGMRES(restart); 1: PCG (precond 0, 2 or 4);
                      2: GPCG[1] (one stored direction); 3: block Gauss-Seidel iteration
-                     x <- x + B^{-1}(F - A x).  Solvers 1-3 need prec SG_F64. */
-    int precond;  /* 0: block-diagonal B_D (Sec. 4.1); 1: block-triangular B_T (Sec. 4.2);
-                     2: block symmetric Gauss-Seidel B_S (Sec. 4.2) */
+                     x <- x + B^{-1}(F - A x); 4: GMRES(restart) preconditioned from the left,
+                     stopping when ||B^{-1}(F - A U)|| / ||B^{-1} F|| < rtol (the convention of the
+                     MATLAB environment Sec. 6 names; a reading of its GMRes(10)).
+                     Solvers 1-4 need prec SG_F64. */
+    int precond;  /* 0: block-diagonal B_D (Sec. 4.1); 1: block-triangular B_T (Sec. 4.2), one
+                     block per degree level; 2: block symmetric Gauss-Seidel B_S (Sec. 4.2), same
+                     blocks; 3: B_T with the 2 x 2 split of Sec. 4.2 (see sg_precond_split);
+                     4: its symmetric B_S.  3 and 4 need prec SG_F64 and SG_COLOUR_LEX. */
     int prec;     /* SG_F64: double V-cycles; SG_MIXED: float V-cycles, double Krylov and residuals */
     int restart;  /* FGMRES restart length, 1..64 */
     int max_it;   /* maximum total iterations */
@@ -177,6 +182,26 @@ int sg_precond_tri(sg_ctx* ctx, const void* R, void* Z, int prec);
  * Symmetric positive definite for double V-cycles (used with PCG).
  * Precisions as sg_precond_diag. */
 int sg_precond_sym(sg_ctx* ctx, const void* R, void* Z, int prec);
+
+/* Z = B^{-1} R for the 2 x 2 split of Sec. 4.2, eq. (hierarchical_structure):
+ * A = [[A_hat, W^T], [W, D]] with A_hat the stochastic Galerkin matrix of the
+ * modes of degree <= p-1 and D = I (x) K_0 that of the degree-p modes.
+ * symmetric 0: B = B_T = [[A_hat, 0], [W, D]], so z1 = A_hat^{-1} r1 and
+ * z2 = D^{-1}(r2 - W z1).  symmetric 1: B = B_S = B_T blockdiag(A_hat, D)^{-1} B_T^T
+ * (the last display of Sec. 4.2), i.e. afterwards z1 <- z1 - A_hat^{-1} W^T z2.
+ * Every diagonal block is solved inexactly by one multigrid V(nu1, nu2) cycle,
+ * as Table 3's caption has it: A_hat by a cycle for the coupled system (Galerkin
+ * coarse operators sum_k G_k (x) P^T K_k P, transfer I (x) P, point Gauss-Seidel
+ * on the assembled A_hat_l in its natural order -- mode by mode, inside a mode
+ * node by node, x fastest -- forward before and backward after the coarse
+ * correction, the coarsest level solved directly), D by one K_0 V-cycle per mode.
+ * R, Z: device doubles, N x P node-major.  Double precision only.  The first
+ * call builds the coupled hierarchy (host Galerkin products, the coarsest A_hat
+ * inverted) and allocates its buffers (about 4 N P doubles).  SG_EINVAL when
+ * p < 1, the context's colour mode is not SG_COLOUR_LEX, or the coarsest A_hat
+ * has more than 2048 unknowns ((coarsest_cells - 1)^2 times the number of
+ * modes of degree <= p-1). */
+int sg_precond_split(sg_ctx* ctx, const double* R, double* Z, int symmetric);
 
 /* Solve A U = F (Sec. 4.2 with Sec. 6 stopping rule).  F, U: device doubles
  * (U holds x0 if opts->use_x0).  info: host, may be NULL.  Returns SG_OK,

@@ -25,7 +25,7 @@ SG_DISC_Q1, SG_DISC_P1 = 0, 1
 DISCRETIZATIONS = {"q1": SG_DISC_Q1, "p1": SG_DISC_P1}
 
 EXPORTED = ["sg_setup", "sg_query", "sg_get_cell_coeffs", "sg_rhs", "sg_apply", "sg_residual", "sg_vcycle",
-            "sg_precond_diag", "sg_precond_tri", "sg_precond_sym", "sg_solve", "sg_qoi", "sg_qoi_noalloc", "sg_qoi_grad",
+            "sg_precond_diag", "sg_precond_tri", "sg_precond_sym", "sg_precond_split", "sg_solve", "sg_qoi", "sg_qoi_noalloc", "sg_qoi_grad",
             "sg_setup_host", "sg_sync",
             "sg_destroy", "sg_last_error"]
 
@@ -81,6 +81,7 @@ def load_library():
         "sg_precond_diag": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "sg_precond_tri": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "sg_precond_sym": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
+        "sg_precond_split": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "sg_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
         "sg_qoi": (ctypes.c_int, [vp, vp, dp, dp]),
         "sg_qoi_noalloc": (ctypes.c_int, [vp, vp, vp, vp]),
@@ -119,8 +120,8 @@ def _dptr(arr):
 
 def solve_options(solver="fgmres", precond="tri", prec=SG_F64, restart=30, max_it=500, rtol=1e-8,
                   use_x0=False, timing=False):
-    return SolveOpts(solver={"fgmres": 0, "pcg": 1, "gpcg": 2, "bgs": 3}[solver],
-                     precond={"diag": 0, "tri": 1, "sym": 2}[precond], prec=prec,
+    return SolveOpts(solver={"fgmres": 0, "pcg": 1, "gpcg": 2, "bgs": 3, "gmres_left": 4}[solver],
+                     precond={"diag": 0, "tri": 1, "sym": 2, "tri2x2": 3, "sym2x2": 4}[precond], prec=prec,
                      restart=restart, max_it=max_it, rtol=rtol, use_x0=int(use_x0), timing=int(timing))
 
 
@@ -243,8 +244,15 @@ class Problem:
         dz = torch.float32 if prec == SG_MIXED else torch.float64
         Z = self.empty(dz) if Z is None else Z
         lib = load_library()
+        shp = (self.N, self.P)
+        if kind in ("tri2x2", "sym2x2"):
+            if prec != SG_F64:
+                raise ValueError("the 2x2 split preconditioners run in double only")
+            _check(lib.sg_precond_split(self._ctx, self._t(R, torch.float64, shp), self._t(Z, dz, shp),
+                                        int(kind == "sym2x2")))
+            return Z
         fn = {"tri": lib.sg_precond_tri, "diag": lib.sg_precond_diag, "sym": lib.sg_precond_sym}[kind]
-        _check(fn(self._ctx, self._t(R, torch.float64, (self.N, self.P)), self._t(Z, dz, (self.N, self.P)), prec))
+        _check(fn(self._ctx, self._t(R, torch.float64, shp), self._t(Z, dz, shp), prec))
         return Z
 
     def solve(self, F=None, U=None, **kw):

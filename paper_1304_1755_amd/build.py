@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgbt.so")
-SOURCES = ["sg_setup.cpp", "sg_apply.hip", "sg_apply_p1.hip", "sg_mg.hip", "sg_vec.hip", "sg_api.hip"]
+SOURCES = ["sg_setup.cpp", "sg_apply.hip", "sg_apply_p1.hip", "sg_mg.hip", "sg_vec.hip", "sg_split.hip", "sg_api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]

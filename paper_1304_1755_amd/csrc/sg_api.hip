@@ -231,7 +231,98 @@ int precond_sym(sg_ctx* c, const double* R, void* Z, int zf) {
     return SG_OK;
 }
 
+// ------------------------------------------------------------------ the 2 x 2 split (Sec. 4.2)
+// B_T = [[A_hat, 0], [W, D]] with A_hat the modes of degree <= p-1 and
+// D = I (x) K_0 those of degree p: z1 = A_hat^{-1} r1 by one coupled V-cycle,
+// z2 = D^{-1} (r2 - W z1) by one K_0 V-cycle per mode.  The symmetric variant
+// B_S = B_T blockdiag(A_hat, D)^{-1} B_T^T then takes z1 <- z1 - A_hat^{-1} W^T z2.
+int ensure_split(sg_ctx* c) {
+    SplitDev& d = c->split;
+    if (d.ready) return SG_OK;
+    if (c->opt.colour_mode != SG_COLOUR_LEX) {
+        set_error("split preconditioner: needs SG_COLOUR_LEX (point Gauss-Seidel in the natural order)");
+        return SG_EINVAL;
+    }
+    SplitHost h;
+    int rc = split_setup(c->hs, h);
+    if (rc) return rc;
+    if ((rc = ensure_mg(c, 0))) return rc;
+    const int L = (int)c->levels.size(), p = c->hs.p;
+    d.Pa = h.Pa;
+    d.npart = h.npart;
+    d.gmax = 0;
+    for (int dd = 0; dd < p; ++dd) d.gmax = std::max(d.gmax, c->hs.offsets[dd + 1] - c->hs.offsets[dd]);
+    d.sten.assign(L, nullptr);
+    d.u.assign(L, nullptr);
+    d.f.assign(L, nullptr);
+    d.r.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+        const size_t cap = (size_t)c->levels[l].N * d.Pa;
+        if ((rc = upload(c, &d.sten[l], h.sten[l]))) return rc;
+        if (l > 0 && ((rc = dalloc(c, &d.u[l], cap)) || (rc = dalloc(c, &d.f[l], cap)))) return rc;
+        if (l < L - 1 && (rc = dalloc(c, &d.r[l], cap))) return rc;
+    }
+    const size_t N0 = c->levels[0].N;
+    if ((rc = upload(c, &d.pidx, h.pidx)) || (rc = upload(c, &d.pcoef, h.pcoef)) || (rc = upload(c, &d.cinv, h.cinv)) ||
+        (rc = dalloc(c, &d.g, N0 * d.gmax)) || (rc = dalloc(c, &d.s1, N0 * d.Pa)) || (rc = dalloc(c, &d.s2, N0 * d.Pa)))
+        return rc;
+    d.ready = 1;
+    return SG_OK;
+}
+
+// u = one V(nu1, nu2) cycle for A_hat_l u = f on level l from u = 0 (N_l x Pa
+// blocks, row strides ldf, ldu): point Gauss-Seidel in the natural order of
+// A_hat_l, forward before and backward after the coarse correction, the
+// coarsest level solved directly
+int split_cycle(sg_ctx* c, int l, const double* f, int ldf, double* u, int ldu) {
+    SplitDev& d = c->split;
+    const int L = (int)c->levels.size() - 1, Pa = d.Pa, N = c->levels[l].N, p = c->hs.p;
+    const auto& off = c->hs.offsets;
+    if (l == L) return launch_split_coarse(c, f, ldf, u, ldu);
+    int rc = launch_fill(c->stream, u, 0, ldu, N, Pa);
+    if (rc) return rc;
+    auto sweep = [&](bool reverse) {
+        for (int i = 0; i < p; ++i) {
+            const int dd = reverse ? p - 1 - i : i, lo = off[dd], w = off[dd + 1] - lo;
+            int e = launch_split_couple(c, l, u, ldu, f, ldf, d.g, w, lo, w, 0);
+            if (!e) e = launch_lex_sweep(c, l, u + lo, ldu, d.g, w, w, reverse ? 1 : 0);
+            if (e) return e;
+        }
+        return (int)SG_OK;
+    };
+    for (int s = 0; s < c->opt.nu1; ++s)
+        if ((rc = sweep(false))) return rc;
+    if ((rc = launch_split_couple(c, l, u, ldu, f, ldf, d.r[l], Pa, 0, Pa, 1))) return rc;
+    if ((rc = launch_restrict_block(c, l, d.r[l], Pa, d.f[l + 1], Pa, Pa))) return rc;
+    if ((rc = split_cycle(c, l + 1, d.f[l + 1], Pa, d.u[l + 1], Pa))) return rc;
+    if ((rc = launch_prolong_block(c, l, d.u[l + 1], Pa, u, ldu, Pa))) return rc;
+    for (int s = 0; s < c->opt.nu2; ++s)
+        if ((rc = sweep(true))) return rc;
+    return SG_OK;
+}
+
+int precond_split(sg_ctx* c, const double* R, double* Z, int sym) {
+    int rc = ensure_split(c);
+    if (rc) return rc;
+    const SplitDev& d = c->split;
+    const int P = c->hs.P, N = c->hs.N, p = c->hs.p, Pa = d.Pa, Pd = P - Pa;
+    const auto& off = c->hs.offsets;
+    if ((rc = split_cycle(c, 0, R, P, Z, P))) return rc;
+    // W couples degree p only with degree p-1: the lower coupling plan of the top level
+    const Plan& pd = c->plan_down[p];
+    if ((rc = launch_apply(c, pd, Z + pd.in_lo, 0, R + Pa, c->ws.fstage, 0, P, Pd, P))) return rc;
+    if ((rc = launch_vcycle(c, c->ws.fstage, Pd, Z + Pa, P, Pd, 0))) return rc;
+    if (!sym) return SG_OK;
+    // W^T z2 is nonzero in degree p-1 only
+    const Plan& pu = c->plan_up[p - 1];
+    if ((rc = launch_fill(c->stream, d.s1, 0, Pa, N, Pa))) return rc;
+    if ((rc = launch_apply(c, pu, Z + pu.in_lo, 0, nullptr, d.s1 + off[p - 1], 0, P, Pa, P))) return rc;
+    if ((rc = split_cycle(c, 0, d.s1, Pa, d.s2, Pa))) return rc;
+    return launch_axpy_cols(c->stream, d.s2, 0, Pa, Z, P, N, Pa, -1.0);
+}
+
 int apply_precond(sg_ctx* c, int kind, const double* R, void* Z, int zf) {
+    if (kind >= 3) return precond_split(c, R, (double*)Z, kind == 4);
     if (kind == 2) return precond_sym(c, R, Z, zf);
     return kind == 1 ? precond_tri(c, R, Z, zf) : precond_diag(c, R, Z, zf);
 }
@@ -284,8 +375,11 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
     const size_t np = NP(c);
     const int restart = o.restart;
     const int zf = o.prec == SG_MIXED;
+    // left: GMRES on M^{-1} A x = M^{-1} F (solver 4), z_j = u_j and w = M^{-1} A u_j
+    const bool left = o.solver == 4;
     int rc = ensure_krylov(c, restart, zf);
     if (rc) return rc;
+    if (left && !c->ws.lt && (rc = dalloc(c, &c->ws.lt, np))) return rc;
     double* scal = c->ws.scal;
     double* hs = c->ws.host_scal;
     const size_t zes = zf ? sizeof(float) : sizeof(double);
@@ -306,8 +400,9 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
     } xz{c->stream, X, (int)np, !o.use_x0};
     // From X = 0 the first candidate is F itself: when F is 16-byte aligned the
     // first step reads it in place, and |F| comes from that step's dot products.
-    bool u_is_F = !o.use_x0 && (uintptr_t)F % 16 == 0;
-    double nF = 0.0, beta = 0.0;
+    bool u_is_F = !left && !o.use_x0 && (uintptr_t)F % 16 == 0;
+    // nF normalises the stop test: |F| (right), |M^{-1} F| (left); nFt = |F|
+    double nF = 0.0, beta = 0.0, nFt = 0.0;
     if (!u_is_F) {
         SG_HIP_CHECK(vec_dot(c->stream, F, F, np, c->ws.partial, scal));
         if ((rc = fetch(c, scal, 1))) return rc;
@@ -321,17 +416,41 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
             xz.pending = true;
             return SG_OK;
         }
-        // r = F - A X, kept unnormalized as the first candidate V_0
-        beta = nF;
-        if (o.use_x0) {
-            if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+        nFt = nF;
+        if (left) {
+            // candidate V_0 = M^{-1} (F - A X)
+            if ((rc = apply_precond(c, o.precond, F, Vj(0), 0))) return rc;
             SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
             if ((rc = fetch(c, scal, 1))) return rc;
-            beta = std::sqrt(hs[0]);
+            nF = beta = std::sqrt(hs[0]);
+            if (!std::isfinite(nF) || nF == 0.0) {
+                set_error("preconditioned right-hand side norm is not finite or zero");
+                return std::isfinite(nF) ? SG_EBREAKDOWN : SG_ENAN;
+            }
+            info.rel_res_true = 1.0;
+            if (o.use_x0) {
+                if ((rc = launch_apply(c, c->plan_full, X, 0, F, c->ws.lt, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+                SG_HIP_CHECK(vec_dot(c->stream, c->ws.lt, c->ws.lt, np, c->ws.partial, scal));
+                if ((rc = fetch(c, scal, 1))) return rc;
+                info.rel_res_true = std::sqrt(hs[0]) / nFt;
+                if ((rc = apply_precond(c, o.precond, c->ws.lt, Vj(0), 0))) return rc;
+                SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
+                if ((rc = fetch(c, scal, 1))) return rc;
+                beta = std::sqrt(hs[0]);
+            }
         } else {
-            SG_HIP_CHECK(hipMemcpyAsync(Vj(0), F, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            // r = F - A X, kept unnormalized as the first candidate V_0
+            beta = nF;
+            if (o.use_x0) {
+                if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+                SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
+                if ((rc = fetch(c, scal, 1))) return rc;
+                beta = std::sqrt(hs[0]);
+            } else {
+                SG_HIP_CHECK(hipMemcpyAsync(Vj(0), F, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+            }
+            info.rel_res_true = beta / nF;
         }
-        info.rel_res_true = beta / nF;
         if (!std::isfinite(beta)) {
             set_error("initial residual is not finite");
             return SG_ENAN;
@@ -353,13 +472,24 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
         int k = 0;  // columns of this cycle
         for (int j = 0; j < restart; ++j) {
             const double* uj = u_is_F ? F : Vj(j);
-            tm.rec(0, c->stream);
-            if ((rc = apply_precond(c, o.precond, uj, Zj(j), zf))) return rc;
-            tm.rec(1, c->stream);
-            tm.rec(2, c->stream);
-            if ((rc = launch_apply(c, c->plan_full, Zj(j), zf, nullptr, c->ws.w, 0, c->hs.P, c->hs.P, c->hs.P)))
-                return rc;
-            tm.rec(3, c->stream);
+            if (left) {
+                SG_HIP_CHECK(hipMemcpyAsync(Zj(j), uj, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+                tm.rec(2, c->stream);
+                if ((rc = launch_apply(c, c->plan_full, uj, 0, nullptr, c->ws.lt, 0, c->hs.P, c->hs.P, c->hs.P)))
+                    return rc;
+                tm.rec(3, c->stream);
+                tm.rec(0, c->stream);
+                if ((rc = apply_precond(c, o.precond, c->ws.lt, c->ws.w, 0))) return rc;
+                tm.rec(1, c->stream);
+            } else {
+                tm.rec(0, c->stream);
+                if ((rc = apply_precond(c, o.precond, uj, Zj(j), zf))) return rc;
+                tm.rec(1, c->stream);
+                tm.rec(2, c->stream);
+                if ((rc = launch_apply(c, c->plan_full, Zj(j), zf, nullptr, c->ws.w, 0, c->hs.P, c->hs.P, c->hs.P)))
+                    return rc;
+                tm.rec(3, c->stream);
+            }
             tm.rec(4, c->stream);
             SG_HIP_CHECK(vec_dots2(c->stream, c->ws.V, vs, j, uj, c->ws.w, np, c->ws.partial, scal));
             const int nch = j == 0 ? 1 : (j + kDc - 1) / kDc;
@@ -468,11 +598,23 @@ int fgmres(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_sol
         SG_HIP_CHECK(hipMemcpyAsync(scal + 512, hs + 512, k * sizeof(double), hipMemcpyHostToDevice, c->stream));
         SG_HIP_CHECK(vec_combine(c->stream, c->ws.Z, zf, vs, k, scal + 512, X, np, !xz.pending));
         xz.pending = false;
-        if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
-        SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
-        if ((rc = fetch(c, scal, 1))) return rc;
-        beta = std::sqrt(hs[0]);
-        info.rel_res_true = beta / nF;
+        if (left) {
+            // true residual, then the new candidate M^{-1} (F - A X) and its norm
+            if ((rc = launch_apply(c, c->plan_full, X, 0, F, c->ws.lt, 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+            SG_HIP_CHECK(vec_dot(c->stream, c->ws.lt, c->ws.lt, np, c->ws.partial, scal));
+            if ((rc = fetch(c, scal, 1))) return rc;
+            info.rel_res_true = std::sqrt(hs[0]) / nFt;
+            if ((rc = apply_precond(c, o.precond, c->ws.lt, Vj(0), 0))) return rc;
+            SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
+            if ((rc = fetch(c, scal, 1))) return rc;
+            beta = std::sqrt(hs[0]);
+        } else {
+            if ((rc = launch_apply(c, c->plan_full, X, 0, F, Vj(0), 0, c->hs.P, c->hs.P, c->hs.P))) return rc;
+            SG_HIP_CHECK(vec_dot(c->stream, Vj(0), Vj(0), np, c->ws.partial, scal));
+            if ((rc = fetch(c, scal, 1))) return rc;
+            beta = std::sqrt(hs[0]);
+            info.rel_res_true = beta / nF;
+        }
         if (!std::isfinite(beta)) {
             set_error("true residual is not finite");
             return SG_ENAN;
@@ -668,14 +810,15 @@ int block_gs(sg_ctx* c, const double* F, double* X, const sg_solve_opts& o, sg_s
 
 int check_opts(const sg_ctx* c, const sg_solve_opts* o) {
     if (!o) return SG_EINVAL;
-    if (o->solver < 0 || o->solver > 3) return SG_EINVAL;
-    if (o->precond < 0 || o->precond > 2) return SG_EINVAL;
+    if (o->solver < 0 || o->solver > 4) return SG_EINVAL;
+    if (o->precond < 0 || o->precond > 4) return SG_EINVAL;
     if (o->prec != SG_F64 && o->prec != SG_MIXED) return SG_EINVAL;
-    if (o->solver == 0 && (o->restart < 1 || o->restart > kMaxRestart)) return SG_EINVAL;
-    // PCG needs a symmetric preconditioner (B_D or B_S); the CG-type solvers
-    // and the stationary iteration run in double only
-    if (o->solver == 1 && o->precond == 1) return SG_EINVAL;
-    if (o->solver != 0 && o->prec != SG_F64) return SG_EINVAL;
+    if ((o->solver == 0 || o->solver == 4) && (o->restart < 1 || o->restart > kMaxRestart)) return SG_EINVAL;
+    // PCG needs a symmetric preconditioner (B_D or a B_S); everything but
+    // right-preconditioned FGMRES with the level-wise preconditioners runs in
+    // double only
+    if (o->solver == 1 && (o->precond == 1 || o->precond == 3)) return SG_EINVAL;
+    if ((o->solver != 0 || o->precond >= 3) && o->prec != SG_F64) return SG_EINVAL;
     if (o->max_it < 1 || !(o->rtol > 0.0)) return SG_EINVAL;
     (void)c;
     return SG_OK;
@@ -945,6 +1088,14 @@ int sg_precond_sym(sg_ctx* c, const void* R, void* Z, int prec) {
     return precond_sym(c, (const double*)R, Z, prec == SG_MIXED);
 }
 
+int sg_precond_split(sg_ctx* c, const double* R, double* Z, int symmetric) {
+    if (!c || !R || !Z || (symmetric != 0 && symmetric != 1)) {
+        set_error("sg_precond_split: invalid argument");
+        return SG_EINVAL;
+    }
+    return precond_split(c, R, Z, symmetric);
+}
+
 int sg_solve(sg_ctx* c, const double* F, double* U, const sg_solve_opts* opts, sg_solve_info* info_out) {
     if (!c || !F || !U || check_opts(c, opts) != SG_OK) {
         set_error("sg_solve: invalid argument or options");
@@ -963,7 +1114,8 @@ int sg_solve(sg_ctx* c, const double* F, double* U, const sg_solve_opts* opts, s
     auto t0 = std::chrono::steady_clock::now();
     int rc;
     switch (opts->solver) {
-        case 0: rc = fgmres(c, F, U, *opts, info, tm); break;
+        case 0:
+        case 4: rc = fgmres(c, F, U, *opts, info, tm); break;
         case 1: rc = pcg(c, F, U, *opts, info, tm); break;
         case 2: rc = gpcg1(c, F, U, *opts, info, tm); break;
         default: rc = block_gs(c, F, U, *opts, info, tm); break;

@@ -53,6 +53,23 @@ struct HostSetup {
 
 int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_amp, HostSetup& hs);
 
+// The 2 x 2 split of Sec. 4.2, A = [[A_hat, W^T], [W, D]]: A_hat couples the
+// modes of degree <= p-1, D = I (x) K_0 the modes of degree p.  One multigrid
+// cycle for the coupled system A_hat needs, on every level l of the K_0
+// hierarchy, the Galerkin coarse operators of all K_k (A_hat_l = sum_k
+// G_hat_k (x) P^T K_k P), the coupling partners of every mode, and the
+// coarsest A_hat_l inverted.
+struct SplitHost {
+    int Pa = 0;                              // modes of degree <= p - 1
+    int npart = 0;                           // partner positions per mode: 2m (at least 2)
+    std::vector<std::vector<double>> sten;   // per level: (m+1) blocks of N_l x 9, block k = K_k on that level
+    std::vector<int> pidx;                   // Pa x npart: partner beta | (k << 16), k = 1..m; -1 unused
+    std::vector<double> pcoef;               // Pa x npart: G_k(alpha, beta)
+    std::vector<double> cinv;                // (N_c Pa)^2 inverse of the coarsest A_hat_l, index node * Pa + alpha
+};
+constexpr int kSplitMaxCoarse = 2048;        // largest N_c Pa the coarsest direct solve of A_hat takes
+int split_setup(const HostSetup& hs, SplitHost& sp);
+
 // coupling tables of one apply "plan": output modes [out_lo, out_lo+W_out),
 // input modes [in_lo, in_lo+W_in).  Lanes are grouped in slots of 64 (one
 // wavefront each); the K_k u values (k >= 1) of a node row are exchanged
@@ -135,6 +152,7 @@ struct Workspace {
     double* w = nullptr;         // NP
     double* amps = nullptr;      // m KL amplitudes s_k
     double* pcg = nullptr;       // 4 x NP (PCG r, z, p, q)
+    double* lt = nullptr;        // NP: A v before the preconditioner (left-preconditioned GMRES)
     double* partial = nullptr;   // reduction partials
     double* scal = nullptr;      // device scalars (h, norms, y)
     double* host_scal = nullptr; // pinned mirror
@@ -148,6 +166,20 @@ struct Workspace {
     double* dc = nullptr;        // n*n x (m+1)
     double* wS = nullptr;        // N
     double* qv = nullptr;        // P
+};
+
+// device copies of SplitHost and the coupled cycle's work buffers (allocated on first use)
+struct SplitDev {
+    int ready = 0;
+    int Pa = 0, npart = 0, gmax = 0;         // gmax: widest degree block of A_hat
+    std::vector<double*> sten;               // per level, (m+1) x N_l x 9
+    std::vector<double*> u, f, r;            // per level, N_l x Pa (u, f from level 1; r above the coarsest)
+    int* pidx = nullptr;
+    double* pcoef = nullptr;
+    double* cinv = nullptr;
+    double* g = nullptr;                     // N_0 x gmax: coupled right-hand sides of one degree block
+    double* s1 = nullptr;                    // N_0 x Pa staging of the symmetric variant
+    double* s2 = nullptr;
 };
 
 }  // namespace sg
@@ -169,6 +201,7 @@ struct sg_ctx {
     std::vector<sg::Plan> plan_down;  // index d = 1..p: level d-1 -> level d
     std::vector<sg::Plan> plan_up;    // index d = 0..p-1: level d+1 -> level d
     sg::Workspace ws;
+    sg::SplitDev split;
     std::vector<void*> allocations;
 };
 
@@ -186,6 +219,18 @@ int launch_vcycle(sg_ctx* c, const void* f, int ldf, void* u, int ldu, int width
 int launch_cast(hipStream_t s, const void* src, int src_float, int lds, void* dst, int dst_float, int ldd,
                 int rows, int width);
 int launch_fill(hipStream_t s, void* dst, int is_float, int ld, int rows, int width);
+// double blocks of `width` modes on multigrid level l (node-major, row strides as given):
+// fc (level l+1) = P^T r (level l); u (level l) += P ec (level l+1); one lexicographic
+// Gauss-Seidel sweep of K_0 on level l (backward when reverse)
+int launch_restrict_block(sg_ctx* c, int l, const double* r, int ldr, double* fc, int ldc, int width);
+int launch_prolong_block(sg_ctx* c, int l, const double* ec, int ldc, double* u, int ldu, int width);
+int launch_lex_sweep(sg_ctx* c, int l, double* u, int ldu, const double* f, int ldf, int width, int reverse);
+// out[:, t] = f[:, lo+t] - self K_0 u[:, lo+t] - sum_partners G_k(lo+t, beta) K_k u[:, beta] on
+// level l, t = 0..width-1 (sg_split.hip)
+int launch_split_couple(sg_ctx* c, int l, const double* u, int ldu, const double* f, int ldf, double* out, int ldo,
+                        int lo, int width, int self);
+// u = A_hat_c^{-1} f on the coarsest level (both N_c x Pa, row strides ldf, ldu)
+int launch_split_coarse(sg_ctx* c, const double* f, int ldf, double* u, int ldu);
 // dst[:, 0:width] += a * src[:, 0:width] (both float or both double, row strides lds / ldd)
 int launch_axpy_cols(hipStream_t s, const void* src, int is_float, int lds, void* dst, int ldd, int rows, int width,
                      double a);

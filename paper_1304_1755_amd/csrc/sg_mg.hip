@@ -1204,6 +1204,65 @@ __global__ void __launch_bounds__(256) k_gs_lex(const T* __restrict__ sten, cons
     }
 }
 
+// The same sweep for grids of at most kLexWaveMaxNx nodes per side, one
+// wavefront per right-hand-side column: the column and its right-hand side
+// sit in LDS, lane y owns grid row y, and at front d every lane relaxes node
+// (d - 2y, y) of its row.  A single wavefront needs no workgroup barrier
+// between fronts (the LDS operations of a wavefront complete in issue order;
+// the wavefront-scope fences keep the compiler from moving LDS accesses across
+// a front), and each lane loads the stencils of its next kLexAhead nodes ahead.
+// Same arithmetic as k_gs_lex.
+constexpr int kLexWaveMaxNx = 63;  // u and f of a 63 x 63 double grid: 62 KB of LDS
+constexpr int kLexAhead = 4;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_lex_wave(const T* __restrict__ sten, const T* __restrict__ rdiag, T* u,
+                                                 int ldu, const T* __restrict__ f, int ldf, int nx, int reverse,
+                                                 int zero_start) {
+    extern __shared__ char smem_raw[];
+    T* us = (T*)smem_raw;
+    T* fs = us + nx * nx;
+    const int col = blockIdx.x, y = threadIdx.x, N = nx * nx;
+    for (int i = y; i < N; i += 64) {
+        us[i] = zero_start ? T(0) : u[(size_t)i * ldu + col];
+        fs[i] = f[(size_t)i * ldf + col];
+    }
+    wave_sync();
+    const int nd = 3 * (nx - 1) + 1;
+    auto node_at = [&](int di) -> int {
+        const int d = reverse ? nd - 1 - di : di, x = d - 2 * y;
+        return (di < nd && y < nx && x >= 0 && x < nx) ? y * nx + x : -1;
+    };
+    T st[kLexAhead][9], rd[kLexAhead];
+    auto fetch = [&](int j, int di) {
+        const int node = max(node_at(di), 0);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) st[j][t] = sten[(size_t)node * 9 + t];
+        rd[j] = rdiag[node];
+    };
+#pragma unroll
+    for (int j = 0; j < kLexAhead; ++j) fetch(j, j);
+    for (int di0 = 0; di0 < nd; di0 += kLexAhead) {
+#pragma unroll
+        for (int j = 0; j < kLexAhead; ++j) {
+            const int node = node_at(di0 + j);
+            if (node >= 0) {
+                const int x = node - y * nx;
+                us[node] = relax_node<T>(st[j], rd[j], fs[node], x, y, nx, [&](int i) { return us[i]; });
+            }
+            fetch(j, di0 + j + kLexAhead);
+            wave_sync();
+        }
+    }
+    for (int i = y; i < N; i += 64) u[(size_t)i * ldu + col] = us[i];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const double* __restrict__ kinv,
                                                       const T* __restrict__ fin, int ldf, T* __restrict__ uout,
@@ -1709,9 +1768,13 @@ void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, boo
     Level& lv = c->levels[l];
     const int nx = lv.nx;
     if (c->opt.colour_mode == SG_COLOUR_LEX) {
-        hipLaunchKernelGGL(k_gs_lex<T>, dim3(width), dim3(256), 0, c->stream, LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv),
-                           u, ldu, f, ldf, nx,
-                           reverse ? 1 : 0, first ? 1 : 0);
+        if (nx <= kLexWaveMaxNx)
+            hipLaunchKernelGGL(k_lex_wave<T>, dim3(width), dim3(64), (size_t)2 * lv.N * sizeof(T), c->stream,
+                               LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv), u, ldu, f, ldf, nx, reverse ? 1 : 0,
+                               first ? 1 : 0);
+        else
+            hipLaunchKernelGGL(k_gs_lex<T>, dim3(width), dim3(256), 0, c->stream, LevelPtr<T>::s(lv),
+                               LevelPtr<T>::rd(lv), u, ldu, f, ldf, nx, reverse ? 1 : 0, first ? 1 : 0);
         return;
     }
     const bool rb = c->opt.colour_mode == SG_COLOUR_RB;
@@ -2077,6 +2140,38 @@ int launch_fill(hipStream_t s, void* dst, int is_float, int ld, int rows, int wi
     else
         hipLaunchKernelGGL(k_fill<double>, grid2(rows, width, tl), dim3(tl.tx, tl.ty), 0, s, (double*)dst, ld,
                            rows, width);
+    return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
+}
+
+int launch_restrict_block(sg_ctx* c, int l, const double* r, int ldr, double* fc, int ldc, int width) {
+    const Tile tl = tile_for(width);
+    const Level& lc = c->levels[l + 1];
+    hipLaunchKernelGGL(k_restrict<double>, grid2(lc.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream, r, ldr, fc, ldc,
+                       lc.nx, width, c->hs.disc == SG_DISC_P1 ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
+}
+
+int launch_prolong_block(sg_ctx* c, int l, const double* ec, int ldc, double* u, int ldu, int width) {
+    const Tile tl = tile_for(width);
+    const Level& lv = c->levels[l];
+    const int p1 = c->hs.disc == SG_DISC_P1 ? 1 : 0;
+    if (tl.tx == 64)
+        hipLaunchKernelGGL((k_prolong_add<double, true>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                           ec, ldc, u, ldu, lv.nx, width, p1);
+    else
+        hipLaunchKernelGGL((k_prolong_add<double, false>), grid2(lv.N, width, tl), dim3(tl.tx, tl.ty), 0, c->stream,
+                           ec, ldc, u, ldu, lv.nx, width, p1);
+    return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
+}
+
+int launch_lex_sweep(sg_ctx* c, int l, double* u, int ldu, const double* f, int ldf, int width, int reverse) {
+    const Level& lv = c->levels[l];
+    if (lv.nx <= kLexWaveMaxNx)
+        hipLaunchKernelGGL(k_lex_wave<double>, dim3(width), dim3(64), (size_t)2 * lv.N * sizeof(double), c->stream,
+                           lv.sten64, lv.rdiag64, u, ldu, f, ldf, lv.nx, reverse, 0);
+    else
+        hipLaunchKernelGGL(k_gs_lex<double>, dim3(width), dim3(256), 0, c->stream, lv.sten64, lv.rdiag64, u, ldu, f,
+                           ldf, lv.nx, reverse, 0);
     return hipGetLastError() == hipSuccess ? SG_OK : SG_EHIP;
 }
 

@@ -180,6 +180,54 @@ std::vector<double> rap(const std::vector<double>& Sf, int nf, bool p1) {
     return Sc;
 }
 
+// The fine-grid operator K_k (k = 0..m) as 9-point stencils on the interior
+// nodes, (dy, dx) row-major, node (x, y) at y*nx + x, nx = n - 1.
+//   SG_DISC_Q1: node (x, y) touches cells SW (x, y), SE (x+1, y), NW (x, y+1)
+//   and NE (x+1, y+1); with the coefficient c of a cell, its element matrix
+//   has entries 4c/6 (own vertex), -c/6 (edge neighbour), -2c/6 (opposite
+//   vertex).
+//   SG_DISC_P1: the 5-point operator sum_e w_{k,e} (u_i - u_j) over the grid
+//   edges, from the east and north edge weights of every grid vertex; node
+//   (x, y) is vertex (x+1, y+1).
+std::vector<double> fine_stencil(const HostSetup& hs, int k) {
+    const int n = hs.n, nx = n - 1, m = hs.m;
+    const size_t ncell = (size_t)n * n;
+    std::vector<double> st((size_t)nx * nx * 9, 0.0);
+    if (hs.disc != SG_DISC_P1) {
+        const double* c = &hs.cellc[(size_t)k * ncell];
+        for (int y = 0; y < nx; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const double sw = c[(size_t)y * n + x], se = c[(size_t)y * n + x + 1];
+                const double nw = c[(size_t)(y + 1) * n + x], ne = c[(size_t)(y + 1) * n + x + 1];
+                double* s = &st[((size_t)y * nx + x) * 9];
+                s[0] = -2.0 * sw / 6.0;          // (-1,-1)
+                s[1] = -(sw + se) / 6.0;         // ( 0,-1)
+                s[2] = -2.0 * se / 6.0;          // (+1,-1)
+                s[3] = -(sw + nw) / 6.0;         // (-1, 0)
+                s[4] = 4.0 * (sw + se + nw + ne) / 6.0;
+                s[5] = -(se + ne) / 6.0;         // (+1, 0)
+                s[6] = -2.0 * nw / 6.0;          // (-1,+1)
+                s[7] = -(nw + ne) / 6.0;         // ( 0,+1)
+                s[8] = -2.0 * ne / 6.0;          // (+1,+1)
+            }
+        return st;
+    }
+    const int W = 2 * (m + 1);
+    auto ew = [&](int vx, int vy) { return hs.kcoef[((size_t)vy * n + vx) * W + k]; };
+    auto nw = [&](int vx, int vy) { return hs.kcoef[((size_t)vy * n + vx) * W + m + 1 + k]; };
+    for (int y = 0; y < nx; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const double wE = ew(x + 1, y + 1), wW = ew(x, y + 1), wN = nw(x + 1, y + 1), wS = nw(x + 1, y);
+            double* s9 = &st[((size_t)y * nx + x) * 9];
+            s9[1] = -wS;
+            s9[3] = -wW;
+            s9[4] = wE + wW + wN + wS;
+            s9[5] = -wE;
+            s9[7] = -wN;
+        }
+    return st;
+}
+
 // f = 2 (1/2 - x^2 - y^2) on (-1/2, 1/2)^2 (Sec. 6)
 double paper_load(double x, double y) { return 2.0 * (0.5 - x * x - y * y); }
 
@@ -266,30 +314,8 @@ int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_a
                 if (e == 0 || margin < hs.a_min_h) hs.a_min_h = margin;
             }
 
-        // fine K_0 stencil from the cell means: node (x, y) touches cells
-        // SW (x, y), SE (x+1, y), NW (x, y+1), NE (x+1, y+1); element matrix
-        // entries 4/6 (own vertex), -1/6 (edge neighbour), -2/6 (opposite vertex).
-        {
-            const int nx = n - 1;
-            std::vector<double> st((size_t)nx * nx * 9, 0.0);
-            for (int y = 0; y < nx; ++y)
-                for (int x = 0; x < nx; ++x) {
-                    const double sw = hs.cellc[(size_t)y * n + x], se = hs.cellc[(size_t)y * n + x + 1];
-                    const double nw = hs.cellc[(size_t)(y + 1) * n + x], ne = hs.cellc[(size_t)(y + 1) * n + x + 1];
-                    double* s = &st[((size_t)y * nx + x) * 9];
-                    s[0] = -2.0 * sw / 6.0;          // (-1,-1)
-                    s[1] = -(sw + se) / 6.0;         // ( 0,-1)
-                    s[2] = -2.0 * se / 6.0;          // (+1,-1)
-                    s[3] = -(sw + nw) / 6.0;         // (-1, 0)
-                    s[4] = 4.0 * (sw + se + nw + ne) / 6.0;
-                    s[5] = -(se + ne) / 6.0;         // (+1, 0)
-                    s[6] = -2.0 * nw / 6.0;          // (-1,+1)
-                    s[7] = -(nw + ne) / 6.0;         // ( 0,+1)
-                    s[8] = -2.0 * ne / 6.0;          // (+1,+1)
-                }
-            hs.mg_n.push_back(n);
-            hs.mg_sten.push_back(std::move(st));
-        }
+        hs.mg_n.push_back(n);
+        hs.mg_sten.push_back(fine_stencil(hs, 0));
         hs.kcoef.assign(ncell * (m + 1), 0.0);
         for (size_t e = 0; e < ncell; ++e)
             for (int k = 0; k <= m; ++k) hs.kcoef[e * (m + 1) + k] = hs.cellc[(size_t)k * ncell + e] / 6.0;
@@ -339,23 +365,9 @@ int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_a
                     w[k] = 0.5 * (tri(k, 0, cx, cy) + tri(k, 1, cx, cy - 1));
                     w[m + 1 + k] = 0.5 * (tri(k, 1, cx, cy) + tri(k, 0, cx - 1, cy));
                 }
-        // fine K_0 in the 9-point format: node (x, y) is vertex (x+1, y+1)
-        const int nx = n - 1;
-        std::vector<double> st((size_t)nx * nx * 9, 0.0);
-        auto ew = [&](int vx, int vy) { return hs.kcoef[((size_t)vy * n + vx) * W]; };
-        auto nw = [&](int vx, int vy) { return hs.kcoef[((size_t)vy * n + vx) * W + m + 1]; };
-        for (int y = 0; y < nx; ++y)
-            for (int x = 0; x < nx; ++x) {
-                const double wE = ew(x + 1, y + 1), wW = ew(x, y + 1), wN = nw(x + 1, y + 1), wS = nw(x + 1, y);
-                double* s9 = &st[((size_t)y * nx + x) * 9];
-                s9[1] = -wS;
-                s9[3] = -wW;
-                s9[4] = wE + wW + wN + wS;
-                s9[5] = -wE;
-                s9[7] = -wN;
-            }
         hs.mg_n.push_back(n);
-        hs.mg_sten.push_back(std::move(st));
+        hs.mg_sten.push_back(fine_stencil(hs, 0));
+        const int nx = n - 1;
         // load vector: f phi_i is a cubic on every triangle; the rule with the
         // centroid (weight -27/48) and the three points (3/5, 1/5, 1/5) in
         // barycentric coordinates (weights 25/48) is exact for cubics
@@ -408,6 +420,85 @@ int host_setup(const sg_options& opt, const double* a0_nodal, const double* kl_a
         hs.coarse_inv.swap(A);
     }
     return hs.a_min_h > 0.0 ? SG_OK : SG_WNOTCOERCIVE;
+}
+
+int split_setup(const HostSetup& hs, SplitHost& sp) {
+    const int m = hs.m, p = hs.p;
+    if (p < 1) {
+        set_error("split preconditioner: needs p >= 1 (A_hat holds the modes of degree <= p - 1)");
+        return SG_EINVAL;
+    }
+    const bool p1 = hs.disc == SG_DISC_P1;
+    const int Pa = hs.offsets[p], nlev = (int)hs.mg_n.size();
+    const int nxc = hs.mg_n.back() - 1, Nc = nxc * nxc, nA = Nc * Pa;
+    if (nA > kSplitMaxCoarse) {
+        set_error("split preconditioner: the coarsest A_hat has " + std::to_string(nA) + " unknowns (limit " +
+                  std::to_string(kSplitMaxCoarse) + "); use a coarser coarsest grid");
+        return SG_EINVAL;
+    }
+    sp.Pa = Pa;
+    sp.npart = 2 * std::max(m, 1);
+    // K_k on every level: the fine operator, then Galerkin coarsening with the
+    // transfer of the K_0 hierarchy
+    sp.sten.assign(nlev, {});
+    for (int k = 0; k <= m; ++k) {
+        std::vector<double> s = fine_stencil(hs, k);
+        for (int l = 0; l < nlev; ++l) {
+            if (l > 0) s = rap(s, hs.mg_n[l - 1], p1);
+            sp.sten[l].insert(sp.sten[l].end(), s.begin(), s.end());
+        }
+    }
+    // partners inside A_hat: G_k(alpha, alpha + e_k) = gscale b_{alpha_k + 1},
+    // G_k(alpha, alpha - e_k) = gscale b_{alpha_k}; G_k(alpha, alpha) = 0
+    std::map<std::vector<int>, int> pos;
+    for (int a = 0; a < hs.P; ++a)
+        pos[std::vector<int>(hs.midx.begin() + (size_t)a * m, hs.midx.begin() + (size_t)(a + 1) * m)] = a;
+    sp.pidx.assign((size_t)Pa * sp.npart, -1);
+    sp.pcoef.assign((size_t)Pa * sp.npart, 0.0);
+    for (int a = 0; a < Pa; ++a) {
+        const std::vector<int> al(hs.midx.begin() + (size_t)a * m, hs.midx.begin() + (size_t)(a + 1) * m);
+        int j = 0;
+        for (int k = 0; k < m; ++k)
+            for (int dir = 0; dir < 2; ++dir) {
+                if (dir == 1 && al[k] == 0) continue;
+                std::vector<int> b = al;
+                b[k] += dir == 0 ? 1 : -1;
+                const auto it = pos.find(b);
+                if (it == pos.end() || it->second >= Pa) continue;
+                sp.pidx[(size_t)a * sp.npart + j] = it->second | ((k + 1) << 16);
+                sp.pcoef[(size_t)a * sp.npart + j] = hs.gscale * legendre_b(dir == 0 ? al[k] + 1 : al[k]);
+                ++j;
+            }
+    }
+    // the coarsest A_hat_l, node-major (row node * Pa + alpha), inverted
+    std::vector<double> A((size_t)nA * nA, 0.0);
+    const std::vector<double>& sc = sp.sten.back();
+    for (int y = 0; y < nxc; ++y)
+        for (int x = 0; x < nxc; ++x) {
+            const int i = y * nxc + x;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int X = x + dx, Y = y + dy;
+                    if (X < 0 || Y < 0 || X >= nxc || Y >= nxc) continue;
+                    const int jn = Y * nxc + X, t = (dy + 1) * 3 + (dx + 1);
+                    for (int a = 0; a < Pa; ++a) {
+                        double* row = &A[((size_t)i * Pa + a) * nA + (size_t)jn * Pa];
+                        row[a] += sc[(size_t)i * 9 + t];
+                        for (int q = 0; q < sp.npart; ++q) {
+                            const int e = sp.pidx[(size_t)a * sp.npart + q];
+                            if (e < 0) continue;
+                            const int b = e & 0xFFFF, k = e >> 16;
+                            row[b] += sp.pcoef[(size_t)a * sp.npart + q] * sc[((size_t)k * Nc + i) * 9 + t];
+                        }
+                    }
+                }
+        }
+    if (!cholesky_inverse(A, nA)) {
+        set_error("split preconditioner: the coarsest A_hat is not positive definite");
+        return SG_EINVAL;
+    }
+    sp.cinv.swap(A);
+    return SG_OK;
 }
 
 PlanHost make_plan(const HostSetup& hs, int in_lo, int W_in, int out_lo, int W_out, bool self, bool up, bool down) {
