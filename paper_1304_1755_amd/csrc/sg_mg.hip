@@ -1113,25 +1113,103 @@ __device__ __forceinline__ void lex_front(int d, int nx, int& ylo, int& yhi) {
     yhi = min(nx - 1, d / 2);
 }
 
+// Lexicographic sweeps by one wavefront, for grids of at most kLexWaveMaxNx
+// nodes per side held in LDS (u and f, nx x nx each): lane y owns grid row y,
+// and at front d every lane relaxes node (d - 2y, y) of its row.  One
+// wavefront needs no workgroup barrier between fronts (the LDS operations of a
+// wavefront complete in issue order; the wavefront-scope fences keep the
+// compiler from moving LDS accesses across a front).  Each lane loads the
+// stencils and right-hand sides of its next kLexAhead nodes ahead of time
+// (f does not change during a sweep), and reads the eight
+// neighbours at clamped addresses (zero outside the grid) so that the reads
+// carry no branches and are issued together.  Same arithmetic as k_gs_lex.
+constexpr int kLexWaveMaxNx = 63;  // u and f of a 63 x 63 double grid: 62 KB of LDS
+constexpr int kLexAhead = 4;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_lex_sweeps(const T* __restrict__ sten, const T* __restrict__ rdiag, T* us,
+                                                const T* fs, int nx, bool reverse, int nu) {
+    const int y = threadIdx.x & 63;
+    const int nd = 3 * (nx - 1) + 1;
+    for (int sweep = 0; sweep < nu; ++sweep) {
+        auto node_at = [&](int di) -> int {
+            const int d = reverse ? nd - 1 - di : di, x = d - 2 * y;
+            return (di < nd && y < nx && x >= 0 && x < nx) ? y * nx + x : -1;
+        };
+        T st[kLexAhead][9], rd[kLexAhead], rf[kLexAhead];
+        auto fetch = [&](int j, int di) {
+            const int node = max(node_at(di), 0);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) st[j][t] = sten[(size_t)node * 9 + t];
+            rd[j] = rdiag[node];
+            rf[j] = fs[node];
+        };
+#pragma unroll
+        for (int j = 0; j < kLexAhead; ++j) fetch(j, j);
+        for (int di0 = 0; di0 < nd; di0 += kLexAhead) {
+#pragma unroll
+            for (int j = 0; j < kLexAhead; ++j) {
+                const int node = node_at(di0 + j);
+                if (node >= 0) {
+                    const int x = node - y * nx;
+                    T v[9];
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int xx = x + dx, yy = y + dy, t = (dy + 1) * 3 + (dx + 1);
+                            const bool in = xx >= 0 && xx < nx && yy >= 0 && yy < nx;
+                            const T w = us[in ? yy * nx + xx : node];
+                            v[t] = in ? w : T(0);
+                        }
+                    T acc = rf[j];
+#pragma unroll
+                    for (int t = 0; t < 9; ++t)
+                        if (t != 4) acc -= st[j][t] * v[t];
+                    us[node] = acc * rd[j];
+                }
+                fetch(j, di0 + j + kLexAhead);
+                wave_sync();
+            }
+        }
+    }
+}
+
+// One lexicographic sweep per right-hand-side column, one wavefront each,
+// the column and its right-hand side staged in LDS.  zero_start: the column
+// starts from zero (not read).
+template <typename T>
+__global__ void __launch_bounds__(64) k_lex_wave(const T* __restrict__ sten, const T* __restrict__ rdiag, T* u,
+                                                 int ldu, const T* __restrict__ f, int ldf, int nx, int reverse,
+                                                 int zero_start) {
+    extern __shared__ char smem_raw[];
+    T* us = (T*)smem_raw;
+    T* fs = us + nx * nx;
+    const int col = blockIdx.x, N = nx * nx;
+    for (int i = threadIdx.x; i < N; i += 64) {
+        us[i] = zero_start ? T(0) : u[(size_t)i * ldu + col];
+        fs[i] = f[(size_t)i * ldf + col];
+    }
+    wave_sync();
+    wave_lex_sweeps<T>(sten, rdiag, us, fs, nx, reverse != 0, 1);
+    for (int i = threadIdx.x; i < N; i += 64) u[(size_t)i * ldu + col] = us[i];
+}
+
 // mode 0: four colours; 1: red/black from start-of-colour values; 2: lexicographic
 template <typename T>
 __device__ void lds_smooth(const T* __restrict__ st, const T* __restrict__ rdiag, T* u, const T* f, T* stage, int nx,
                            int mode, bool reverse,
                            int nu) {
     if (mode == 2) {
-        const int nd = 3 * (nx - 1) + 1;
-        for (int sweep = 0; sweep < nu; ++sweep)
-            for (int di = 0; di < nd; ++di) {
-                const int d = reverse ? nd - 1 - di : di;
-                int ylo, yhi;
-                lex_front(d, nx, ylo, yhi);
-                for (int y = ylo + (int)threadIdx.x; y <= yhi; y += blockDim.x) {
-                    const int x = d - 2 * y, node = y * nx + x;
-                    u[node] = relax_node<T>(st + (size_t)node * 9, rdiag[node], f[node], x, y, nx,
-                                            [&](int i) { return u[i]; });
-                }
-                __syncthreads();
-            }
+        // the first wavefront sweeps (every fused grid has at most 63 rows); the others wait
+        if (threadIdx.x < 64) wave_lex_sweeps<T>(st, rdiag, u, f, nx, reverse, nu);
+        __syncthreads();
         return;
     }
     const bool rb = mode == 1;
@@ -1202,65 +1280,6 @@ __global__ void __launch_bounds__(256) k_gs_lex(const T* __restrict__ sten, cons
         }
         __syncthreads();
     }
-}
-
-// The same sweep for grids of at most kLexWaveMaxNx nodes per side, one
-// wavefront per right-hand-side column: the column and its right-hand side
-// sit in LDS, lane y owns grid row y, and at front d every lane relaxes node
-// (d - 2y, y) of its row.  A single wavefront needs no workgroup barrier
-// between fronts (the LDS operations of a wavefront complete in issue order;
-// the wavefront-scope fences keep the compiler from moving LDS accesses across
-// a front), and each lane loads the stencils of its next kLexAhead nodes ahead.
-// Same arithmetic as k_gs_lex.
-constexpr int kLexWaveMaxNx = 63;  // u and f of a 63 x 63 double grid: 62 KB of LDS
-constexpr int kLexAhead = 4;
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename T>
-__global__ void __launch_bounds__(64) k_lex_wave(const T* __restrict__ sten, const T* __restrict__ rdiag, T* u,
-                                                 int ldu, const T* __restrict__ f, int ldf, int nx, int reverse,
-                                                 int zero_start) {
-    extern __shared__ char smem_raw[];
-    T* us = (T*)smem_raw;
-    T* fs = us + nx * nx;
-    const int col = blockIdx.x, y = threadIdx.x, N = nx * nx;
-    for (int i = y; i < N; i += 64) {
-        us[i] = zero_start ? T(0) : u[(size_t)i * ldu + col];
-        fs[i] = f[(size_t)i * ldf + col];
-    }
-    wave_sync();
-    const int nd = 3 * (nx - 1) + 1;
-    auto node_at = [&](int di) -> int {
-        const int d = reverse ? nd - 1 - di : di, x = d - 2 * y;
-        return (di < nd && y < nx && x >= 0 && x < nx) ? y * nx + x : -1;
-    };
-    T st[kLexAhead][9], rd[kLexAhead];
-    auto fetch = [&](int j, int di) {
-        const int node = max(node_at(di), 0);
-#pragma unroll
-        for (int t = 0; t < 9; ++t) st[j][t] = sten[(size_t)node * 9 + t];
-        rd[j] = rdiag[node];
-    };
-#pragma unroll
-    for (int j = 0; j < kLexAhead; ++j) fetch(j, j);
-    for (int di0 = 0; di0 < nd; di0 += kLexAhead) {
-#pragma unroll
-        for (int j = 0; j < kLexAhead; ++j) {
-            const int node = node_at(di0 + j);
-            if (node >= 0) {
-                const int x = node - y * nx;
-                us[node] = relax_node<T>(st[j], rd[j], fs[node], x, y, nx, [&](int i) { return us[i]; });
-            }
-            fetch(j, di0 + j + kLexAhead);
-            wave_sync();
-        }
-    }
-    for (int i = y; i < N; i += 64) u[(size_t)i * ldu + col] = us[i];
 }
 
 template <typename T>
