@@ -1122,9 +1122,10 @@ __device__ __forceinline__ void lex_front(int d, int nx, int& ylo, int& yhi) {
 // stencils and right-hand sides of its next kLexAhead nodes ahead of time
 // (f does not change during a sweep), and reads the eight
 // neighbours at clamped addresses (zero outside the grid) so that the reads
-// carry no branches and are issued together.  Same arithmetic as k_gs_lex.
+// carry no branches and are issued together.  The relaxation sums the
+// neighbours in two chains (same values as k_gs_lex up to rounding).
 constexpr int kLexWaveMaxNx = 63;  // u and f of a 63 x 63 double grid: 62 KB of LDS
-constexpr int kLexAhead = 4;
+constexpr int kLexAhead = 8;
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1168,11 +1169,15 @@ __device__ __forceinline__ void wave_lex_sweeps(const T* __restrict__ sten, cons
                             const T w = us[in ? yy * nx + xx : node];
                             v[t] = in ? w : T(0);
                         }
-                    T acc = rf[j];
-#pragma unroll
-                    for (int t = 0; t < 9; ++t)
-                        if (t != 4) acc -= st[j][t] * v[t];
-                    us[node] = acc * rd[j];
+                    // two partial sums (rows below and above the node) shorten the dependent chain
+                    T lo = rf[j] - st[j][0] * v[0], hi = st[j][6] * v[6];
+                    lo -= st[j][1] * v[1];
+                    hi += st[j][7] * v[7];
+                    lo -= st[j][2] * v[2];
+                    hi += st[j][8] * v[8];
+                    lo -= st[j][3] * v[3];
+                    hi += st[j][5] * v[5];
+                    us[node] = (lo - hi) * rd[j];
                 }
                 fetch(j, di0 + j + kLexAhead);
                 wave_sync();
