@@ -125,7 +125,8 @@ def cpu_baseline(sgbt, stream, seconds=10.0):
 def paper_table3(sgbt, stream):
     """Iterations and time to 1e-10 of the five solvers of Table 3 on the paper's own problem
     (P1 triangles, h = 1/64, m = 6, p = 4, L = 1, 833,490 unknowns) for sigma = 0.1 .. 0.4, with
-    the four-colour and with the paper's lexicographic V(2,2), beside the printed counts."""
+    the four-colour and with the lexicographic V(2,2) (our reading of Sec. 6's point Gauss-Seidel),
+    and with the 2x2 split of Sec. 4.2, beside the printed counts."""
     golden = {}
     with open(os.path.join(ROOT, "tests", "golden", "paper_numbers.txt")) as fh:
         for line in fh:

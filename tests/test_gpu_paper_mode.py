@@ -221,7 +221,7 @@ def test_table2_counts_are_robust_in_h_and_p():
 @pytest.mark.parametrize("disc,n,width,prec", [("p1", 64, 35, 0), ("p1", 64, 6, 1), ("q1", 64, 21, 0),
                                                  ("q1", 128, 35, 1)])
 def test_lexicographic_vcycle_matches_oracle(disc, n, width, prec):
-    # the smoother of Sec. 6: lexicographic point Gauss-Seidel, forward before and backward
+    # lexicographic point Gauss-Seidel (our reading of Sec. 6's point Gauss-Seidel), forward before and backward
     # after the coarse correction; separate-launch levels and the fused coarse cycle
     note(f"lex vcycle {disc} n={n} width={width} prec={prec}")
     import torch
@@ -243,7 +243,7 @@ def test_lexicographic_vcycle_matches_oracle(disc, n, width, prec):
 
 
 @pytest.mark.parametrize("sigma", [0.1, 0.2, 0.3, 0.4])
-def test_table3_with_the_papers_smoother(sigma):
+def test_table3_with_lexicographic_smoother(sigma):
     # Table 3 with the lexicographic V(2,2) (our reading of Sec. 6's point Gauss-Seidel): the five
     # solvers' counts equal the oracle's (same smoother) within one at every sigma; at sigma = 0.1
     # they are also within one of the printed ones (at larger sigma this reading of B_T gives more
@@ -269,7 +269,7 @@ def test_table3_with_the_papers_smoother(sigma):
             assert abs(it - pp) <= 1, (got, paper)
 
 
-def test_table2_with_the_papers_smoother():
+def test_table2_with_lexicographic_smoother():
     # Table 2 (sigma = 0.1, m = 4, h = 1/32 .. 1/128, p = 2 .. 4) with the lexicographic V(2,2):
     # every count within one of the printed one (BD-PCG 13, BT-GPCG 9, BT-GMRes 8, BS-PCG 9),
     # whatever h and p
