@@ -15,7 +15,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsgbt.so")
+# SGBT_LIBRARY selects another build of the same library (the LDS-poison debug build)
+LIB_PATH = os.environ.get("SGBT_LIBRARY") or os.path.join(_HERE, "libsgbt.so")
 
 SG_OK, SG_WNOTCOERCIVE = 0, 1
 SG_EINVAL, SG_ENOMEM, SG_EHIP, SG_ENOTCONV, SG_ENAN, SG_EBREAKDOWN = -1, -2, -3, -4, -5, -6

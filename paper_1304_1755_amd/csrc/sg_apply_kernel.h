@@ -105,6 +105,7 @@ k_sg_apply(const Tin* __restrict__ U, int ldu, const double* __restrict__ R, int
     uint32_t off[2 * NB];
 #pragma unroll
     for (int j = 0; j < 2 * NB; ++j) off[j] = xoff[t * (kNPos / 2) + j];
+    SG_POISON_LDS(S, RW * NODE);
     if (threadIdx.x < RW) S[threadIdx.x * NODE + MM * LANES] = 0.0;  // zero entries
 
     // Circular window wb[row][c] of mode vectors, rows y0-1 .. y0+RW: column

@@ -27,6 +27,23 @@ void set_error(const std::string& msg);
         }                                                                           \
     } while (0)
 
+// Debug build (-DSG_LDS_POISON, built beside the library as libsgbt_poison.so):
+// every kernel that stages data in LDS tiles first fills its LDS with quiet
+// NaNs and meets at a barrier, so that a value read before it was written
+// turns the kernel's output into NaN.  Normal builds compile it to nothing.
+#ifdef SG_LDS_POISON
+template <typename T>
+__device__ inline void lds_poison(T* p, long count) {
+    const int nt = blockDim.x * blockDim.y * blockDim.z;
+    const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    for (long i = t; i < count; i += nt) p[i] = (T)__builtin_nan("");
+    __syncthreads();
+}
+#define SG_POISON_LDS(ptr, count) ::sg::lds_poison((ptr), (long)(count))
+#else
+#define SG_POISON_LDS(ptr, count) ((void)0)
+#endif
+
 // ---------------------------------------------------------------- host setup
 struct HostSetup {
     int n = 0, m = 0, p = 0, P = 0, N = 0;

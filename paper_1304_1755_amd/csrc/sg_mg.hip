@@ -278,6 +278,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ st
     const int tc = ok ? t : width - 1;
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb >= nxc * nseg) return;  // uniform over the workgroup
+    SG_POISON_LDS(stl, sizeof(stl) / sizeof(T));
     const int Y = lb / nseg;
     const int X0 = (lb - Y * nseg) * SEG;
     const int X1 = min(X0 + SEG, nxc);
@@ -497,6 +498,7 @@ template <typename T>
 __global__ void k_coarse(const double* __restrict__ kinv, const T* __restrict__ f, int ldf, T* __restrict__ u,
                          int ldu, int Nc) {
     extern __shared__ double fs[];
+    SG_POISON_LDS(fs, Nc);
     const int col = blockIdx.x;
     for (int i = threadIdx.x; i < Nc; i += blockDim.x) fs[i] = (double)f[(size_t)i * ldf + col];
     __syncthreads();
@@ -551,6 +553,7 @@ __global__ void __launch_bounds__(256) k_gs_rows(const T* __restrict__ sten, con
     const int tc = ok ? t : width - 1;  // lanes past the block load a valid column and store nothing
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb >= nrows * nseg) return;     // uniform over the workgroup
+    SG_POISON_LDS(stl, sizeof(stl) / sizeof(T));
     const int r = lb / nseg;
     const int y = py + 2 * r;
     const int x0 = (lb - r * nseg) * SEG;  // even
@@ -680,6 +683,7 @@ __global__ void __launch_bounds__(256) k_gs_sweep0(const T* __restrict__ stp, co
     const int tc = ok ? t : width - 1;
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     if (lb >= nrows1 * nseg) return;  // uniform over the workgroup
+    SG_POISON_LDS(stl, sizeof(stl) / sizeof(T));
     const int r = lb / nseg;
     const int y1 = p1 + 2 * r;
     const int x0 = (lb - r * nseg) * SEG;
@@ -889,6 +893,8 @@ __global__ void __launch_bounds__(1024) k_cycle1_down(const T* __restrict__ stp,
                                                       int nu, int ntx, int ntiles, int p1) {
     __shared__ T u[kTileP * kTileP];
     __shared__ T r[(2 * kTileCX + 1) * (2 * kTileCY + 1)];
+    SG_POISON_LDS(u, kTileP * kTileP);
+    SG_POISON_LDS(r, (2 * kTileCX + 1) * (2 * kTileCY + 1));
     constexpr int RW = 2 * kTileCX + 1;
     const int mode = blockIdx.x / ntiles, tile = blockIdx.x - mode * ntiles;
     f += mode;
@@ -944,6 +950,7 @@ __global__ void __launch_bounds__(1024) k_cycle1_up(const T* __restrict__ stp, c
                                                     int ldc, T* __restrict__ uo, int ldo, int nx, int nu, int ntx,
                                                     int ntiles, int p1) {
     __shared__ T u[kTileP * kTileP];
+    SG_POISON_LDS(u, kTileP * kTileP);
     const int mode = blockIdx.x / ntiles, tile = blockIdx.x - mode * ntiles;
     f += mode;
     ui += mode;
@@ -1196,6 +1203,7 @@ __global__ void __launch_bounds__(64) k_lex_wave(const T* __restrict__ sten, con
     extern __shared__ char smem_raw[];
     T* us = (T*)smem_raw;
     T* fs = us + nx * nx;
+    SG_POISON_LDS(us, 2 * nx * nx);
     const int col = blockIdx.x, N = nx * nx;
     for (int i = threadIdx.x; i < N; i += 64) {
         us[i] = zero_start ? T(0) : u[(size_t)i * ldu + col];
@@ -1294,6 +1302,7 @@ __global__ void __launch_bounds__(512) k_vcycle_fused(FusedLevels<T> fl, const d
     extern __shared__ char smem_raw[];
     T* lds = (T*)smem_raw;
     T* r = lds + fl.roff;
+    SG_POISON_LDS(lds, fl.roff + fl.nx[0] * fl.nx[0]);
     const int col = blockIdx.x;
     const int L = fl.nlev - 1;
     {
@@ -1472,6 +1481,7 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_fused4(FusedLeve
     extern __shared__ char smem_raw[];
     T* lds = (T*)smem_raw;
     T* r = lds + fl.roff;
+    SG_POISON_LDS(lds, fl.roff + fl.nx[0] * fl.nx[0]);
     const int col = blockIdx.x;
     const int L = fl.nlev - 1;
     {
@@ -1647,6 +1657,7 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_pad(PadLevels<T>
                                                                     T* __restrict__ uout, int ldu, int nu1, int nu2) {
     extern __shared__ char smem_raw[];
     T* lds = (T*)smem_raw;
+    SG_POISON_LDS(lds, pl.roff + pl.nx[0] * pl.nx[0]);
     const int col = blockIdx.x;
     const int L = pl.nlev - 1;
     const int nx0 = pl.nx[0], N0 = nx0 * nx0;

@@ -192,6 +192,7 @@ __global__ void __launch_bounds__(256) k_combine(const TZ* __restrict__ Z, size_
                                                  bool acc) {
     using TZ2 = typename std::conditional<sizeof(TZ) == 4, float2, double2>::type;
     __shared__ double ys[kMaxRestart];
+    SG_POISON_LDS(ys, kMaxRestart);
     for (int i = threadIdx.x; i < nz; i += blockDim.x) ys[i] = y[i];
     __syncthreads();
     const size_t npair = len / 2;
@@ -236,6 +237,7 @@ __global__ void __launch_bounds__(256) k_combine_scalar(const TZ* __restrict__ Z
                                                         const double* __restrict__ y, double* __restrict__ x,
                                                         size_t len, bool acc) {
     __shared__ double ys[kMaxRestart];
+    SG_POISON_LDS(ys, kMaxRestart);
     for (int i = threadIdx.x; i < nz; i += blockDim.x) ys[i] = y[i];
     __syncthreads();
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
@@ -322,6 +324,7 @@ __global__ void __launch_bounds__(256) k_grad_cells(const double* __restrict__ U
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double* T = lds_raw + wv * (4 * LANES + 2);
+    SG_POISON_LDS(lds_raw, 4 * (4 * LANES + 2));
     const int cellid = blockIdx.x * 4 + wv;
     if (cellid >= n * n) return;
     const int cy = cellid / n, cx = cellid - cy * n;
