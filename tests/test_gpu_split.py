@@ -155,3 +155,42 @@ def test_table3_with_the_2x2_split(sigma):
     note(f"p1 table 3 split sigma {sigma}: gpu {got}, oracle {ref}, paper {paper}")
     for it, r in zip(got, ref):
         assert abs(it - r) <= 1, (got, ref)
+
+
+def oracle_table2(n, p):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_table2_counts.txt")
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line.startswith(f"split_n{n}_p{p} ="):
+                return [int(v) for v in line.split("=", 1)[1].split()]
+    raise KeyError((n, p))
+
+
+def test_table2_with_the_2x2_split():
+    # Table 2 (sigma = 0.1, m = 4, h = 1/32 .. 1/128, p = 2 .. 4) with BD-PCG and with B_T / B_S of
+    # the 2x2 split: the counts equal the oracle's within one (stored by
+    # tests/golden/make_oracle_table2.py, oracle only) and the printed ones (BD-PCG 13, BT-GPCG 9,
+    # BT-GMRes 8, BS-PCG 9) within one, independent of h and p
+    note("p1 table 2 split")
+    import paper_1304_1755_amd as sgbt
+    g0 = golden()
+    paper = [int(g0["table2_iters_BD_PCG"]), int(g0["table2_iters_BT_GPCG"]), int(g0["table2_iters_BT_GMRes"]),
+             int(g0["table2_iters_BT_GPCG"])]
+    runs = [dict(solver="pcg", precond="diag"), dict(solver="gpcg", precond="tri2x2"),
+            dict(solver="gmres_left", precond="tri2x2", restart=10), dict(solver="pcg", precond="sym2x2")]
+    for n in (32, 64, 128):
+        for p in (2, 3, 4):
+            note(f"p1 table 2 split n={n} p={p}")
+            g = sgbt.Problem(n, 4, p, 0.1, corr_len=1.0, coarsest=4, disc="p1", colour="lex")
+            its = []
+            for kw in runs:
+                _, info = g.solve(rtol=1e-10, max_it=300, **kw)
+                assert info["status"] == 0, (n, p, kw)
+                its.append(info["iters"])
+            g.close()
+            ref = oracle_table2(n, p)
+            for it, r, pp in zip(its, ref, paper):
+                assert abs(it - r) <= 1, (n, p, its, ref)
+                assert abs(it - pp) <= 1, (n, p, its, paper)

@@ -145,6 +145,39 @@ def test_literal_reading_reproduces_table3(sigma):
     assert abs(bgs - printed[0]) <= (2 if sigma < 0.4 else 0.1 * printed[0]), (got, printed)
 
 
+def test_literal_reading_reproduces_table2():
+    # Table 2 (sigma = 0.1, m = 4, h = 1/32 .. 1/128, p = 2 .. 4): under the 2x2 split the oracle's
+    # counts (stored by tests/golden/make_oracle_table2.py) are within one of the printed ones,
+    # BD-PCG 13, BT-GPCG 9, BT-GMRes(10) 8, BS-PCG 9, for every h and p
+    g = golden()
+    printed = [int(g["table2_iters_BD_PCG"]), int(g["table2_iters_BT_GPCG"]), int(g["table2_iters_BT_GMRes"]),
+               int(g["table2_iters_BT_GPCG"])]
+    path = os.path.join(HERE, "golden", "oracle_table2_counts.txt")
+    rows = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if "=" in line:
+                k, v = line.split("=", 1)
+                rows[k.strip()] = [int(x) for x in v.split()]
+    assert len(rows) == 9, rows
+    for key, got in rows.items():
+        for it, pp in zip(got, printed):
+            assert abs(it - pp) <= 1, (key, got, printed)
+
+
+def test_table2_split_counts_recomputed_at_h_1_32():
+    # the stored h = 1/32, p = 2 row, recomputed here (under a second on one core)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_oracle_table2", os.path.join(HERE, "golden",
+                                                                                      "make_oracle_table2.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(HERE, "golden", "oracle_table2_counts.txt")) as fh:
+        stored = [line for line in fh if line.startswith("split_n32_p2 =")][0]
+    assert mod.split_counts(32, 2) == [int(v) for v in stored.split("=", 1)[1].split()]
+
+
 @pytest.mark.slow
 def test_stored_literal_counts_are_reproducible():
     # recompute the sigma = 0.1 row (about a minute on one core) and compare with the stored one
