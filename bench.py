@@ -17,7 +17,9 @@ solve of the same problem is timed the same way, for the mixed-vs-double
 comparison, one more solve of each precision is run with per-phase HIP
 event timing (apply / preconditioner / orthogonalisation), and the two
 solutions are compared.  The 1025 x 1025 workload (m = 8, p = 3, P = 165,
-GMRES(20)) is measured the same way in a block of its own.  The oracle (CPU,
+GMRES(20)) is measured the same way in a block of its own, the adjoint
+workload (257 x 257, m = 5, p = 3) by the times of its forward solve and of its
+QoI gradient, and the paper's Sec. 6 problem by the Table 3 solvers.  The oracle (CPU,
 double) is timed on bounded samples of the 65 x 65 copy of the workload (same
 m, p, sigma; 833,490 unknowns): its SG apply, and its block-triangular
 FGMRES(30) solve to 1e-8; its direct solution of that system is the
@@ -181,6 +183,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-paper", action="store_true", help="skip the Sec. 6 iteration-count table")
     ap.add_argument("--no-c4", action="store_true", help="skip the 1025x1025 workload block")
+    ap.add_argument("--no-c5", action="store_true", help="skip the adjoint workload block")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -350,6 +353,9 @@ def main():
     prob.close()
     del F, X, X_mixed
     torch.cuda.empty_cache()
+    if not args.no_c5:
+        progress("the adjoint workload (257x257, m = 5, p = 3, P = 56)")
+        out["c5_adjoint"] = adjoint_workload(sgbt, stream, progress)
     if not args.no_c4:
         progress("the 1025x1025 workload (m = 8, p = 3, P = 165)")
         out["c4"] = second_workload(sgbt, stream, "c4", args.burst, max(2, min(args.steps, 5)), progress)
@@ -360,6 +366,41 @@ def main():
         progress("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(sgbt, stream)
     print(json.dumps(out))
+
+
+def adjoint_workload(sgbt, stream, progress, reps=3):
+    """The adjoint configuration (257x257, m = 5, p = 3, P = 56, sigma = 0.3, seeded a0 noise): time of
+    the forward B_T-FGMRES(30) solve to 1e-8 and of the QoI gradient (adjoint solve of the symmetric
+    system with the same solver, then the cell-gradient and reduction kernels), all double; medians
+    of `reps` runs after one warm-up.  The gradient itself is checked against the oracle's and
+    against central differences by the tests."""
+    import numpy as np
+    import torch
+
+    import sg_inputs
+    c = sg_inputs.CONFIGS["c5"]
+    a0 = sg_inputs.a0_noise_field(c["n"])
+    prob = sgbt.Problem(c["n"], c["m"], c["p"], c["sigma"], c["corr_len"], a0_nodal=a0, stream=stream)
+    F = prob.rhs()
+    X = prob.empty()
+    kw = dict(precond="tri", prec=sgbt.SG_F64, restart=30, rtol=1e-8, max_it=300)
+    fwd, grad = [], []
+    for r in range(reps + 1):
+        _, info = prob.solve(F, X, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gr = prob.qoi_grad(X, **kw)
+        torch.cuda.synchronize()
+        if r > 0:
+            fwd.append(info["t_total_ms"])
+            grad.append((time.perf_counter() - t0) * 1e3)
+    prob.close()
+    progress(f"adjoint: forward {float(np.median(fwd)):.1f} ms, gradient {float(np.median(grad)):.1f} ms")
+    return {"workload": "c5: Q1 257x257 grid (N=65025), m=5, p=3, P=56 (3641400 unknowns), sigma=0.3, L=0.5, "
+                        "a0 = 1 + 0.1 seeded noise; B_T-FGMRES(30) V(2,2), double, to 1e-8",
+            "forward_solve_ms": float(np.median(fwd)), "qoi_gradient_ms": float(np.median(grad)),
+            "forward_iters": info["iters"], "adjoint_iters": gr["adj_info"]["iters"], "J": gr["J"],
+            "gradient_entries": 1 + c["m"] + prob.N}
 
 
 def second_workload(sgbt, stream, name, burst, solves, progress):
