@@ -1131,7 +1131,7 @@ __device__ __forceinline__ void lex_front(int d, int nx, int& ylo, int& yhi) {
 // neighbours at clamped addresses (zero outside the grid) so that the reads
 // carry no branches and are issued together.  The relaxation sums the
 // neighbours in two chains (same values as k_gs_lex up to rounding).
-constexpr int kLexWaveMaxNx = 63;  // u and f of a 63 x 63 double grid: 62 KB of LDS
+constexpr int kLexWaveMaxNx = 63;  // at most 64 rows, one per lane
 constexpr int kLexAhead = 8;
 
 __device__ __forceinline__ void wave_sync() {
@@ -1193,25 +1193,68 @@ __device__ __forceinline__ void wave_lex_sweeps(const T* __restrict__ sten, cons
     }
 }
 
-// One lexicographic sweep per right-hand-side column, one wavefront each,
-// the column and its right-hand side staged in LDS.  zero_start: the column
-// starts from zero (not read).
+// One lexicographic sweep per right-hand-side column, one wavefront each:
+// the column sits in LDS inside a border of zeros ((nx+2)^2 values), so a
+// node's eight neighbours are read at fixed offsets from one address with no
+// bounds tests, and f, the stencils and the reciprocal diagonals (none of
+// which the sweep changes) are loaded from global memory kLexAhead fronts
+// ahead.  zero_start: the column starts from zero (not read).  Same fronts
+// and arithmetic as wave_lex_sweeps.
 template <typename T>
 __global__ void __launch_bounds__(64) k_lex_wave(const T* __restrict__ sten, const T* __restrict__ rdiag, T* u,
                                                  int ldu, const T* __restrict__ f, int ldf, int nx, int reverse,
                                                  int zero_start) {
     extern __shared__ char smem_raw[];
     T* us = (T*)smem_raw;
-    T* fs = us + nx * nx;
-    SG_POISON_LDS(us, 2 * nx * nx);
-    const int col = blockIdx.x, N = nx * nx;
-    for (int i = threadIdx.x; i < N; i += 64) {
-        us[i] = zero_start ? T(0) : u[(size_t)i * ldu + col];
-        fs[i] = f[(size_t)i * ldf + col];
+    const int col = blockIdx.x, pw = nx + 2, N = nx * nx;
+    SG_POISON_LDS(us, pw * pw);
+    for (int i = threadIdx.x; i < pw * pw; i += 64) {
+        const int py = i / pw, px = i - py * pw;
+        const bool in = px >= 1 && px <= nx && py >= 1 && py <= nx;
+        us[i] = (in && !zero_start) ? u[(size_t)((py - 1) * nx + px - 1) * ldu + col] : T(0);
     }
     wave_sync();
-    wave_lex_sweeps<T>(sten, rdiag, us, fs, nx, reverse != 0, 1);
-    for (int i = threadIdx.x; i < N; i += 64) u[(size_t)i * ldu + col] = us[i];
+    const int y = threadIdx.x;
+    const int nd = 3 * (nx - 1) + 1;
+    auto x_at = [&](int di) -> int { return (reverse ? nd - 1 - di : di) - 2 * y; };
+    auto live = [&](int di, int x) { return di < nd && y < nx && x >= 0 && x < nx; };
+    T st[kLexAhead][9], rd[kLexAhead], rf[kLexAhead];
+    auto fetch = [&](int j, int di) {
+        const int x = x_at(di);
+        const int node = live(di, x) ? y * nx + x : 0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) st[j][t] = sten[(size_t)node * 9 + t];
+        rd[j] = rdiag[node];
+        rf[j] = f[(size_t)node * ldf + col];
+    };
+#pragma unroll
+    for (int j = 0; j < kLexAhead; ++j) fetch(j, j);
+    for (int di0 = 0; di0 < nd; di0 += kLexAhead) {
+#pragma unroll
+        for (int j = 0; j < kLexAhead; ++j) {
+            const int x = x_at(di0 + j);
+            if (live(di0 + j, x)) {
+                // b: the south-west neighbour of node (x, y) in the padded grid
+                T* b = us + y * pw + x;
+                const T vSW = b[0], vS = b[1], vSE = b[2], vW = b[pw], vE = b[pw + 2];
+                const T vNW = b[2 * pw], vN = b[2 * pw + 1], vNE = b[2 * pw + 2];
+                T lo = rf[j] - st[j][0] * vSW, hi = st[j][6] * vNW;
+                lo -= st[j][1] * vS;
+                hi += st[j][7] * vN;
+                lo -= st[j][2] * vSE;
+                hi += st[j][8] * vNE;
+                lo -= st[j][3] * vW;
+                hi += st[j][5] * vE;
+                b[pw + 1] = (lo - hi) * rd[j];
+            }
+            fetch(j, di0 + j + kLexAhead);
+            wave_sync();
+        }
+    }
+    for (int i = threadIdx.x; i < N; i += 64) {
+        const int py = i / nx, px = i - py * nx;
+        u[(size_t)i * ldu + col] = us[(py + 1) * pw + px + 1];
+    }
 }
 
 // mode 0: four colours; 1: red/black from start-of-colour values; 2: lexicographic
@@ -1804,7 +1847,7 @@ void smooth(sg_ctx* c, int l, T* u, int ldu, const T* f, int ldf, int width, boo
     const int nx = lv.nx;
     if (c->opt.colour_mode == SG_COLOUR_LEX) {
         if (nx <= kLexWaveMaxNx)
-            hipLaunchKernelGGL(k_lex_wave<T>, dim3(width), dim3(64), (size_t)2 * lv.N * sizeof(T), c->stream,
+            hipLaunchKernelGGL(k_lex_wave<T>, dim3(width), dim3(64), (size_t)(nx + 2) * (nx + 2) * sizeof(T), c->stream,
                                LevelPtr<T>::s(lv), LevelPtr<T>::rd(lv), u, ldu, f, ldf, nx, reverse ? 1 : 0,
                                first ? 1 : 0);
         else
@@ -2202,7 +2245,8 @@ int launch_prolong_block(sg_ctx* c, int l, const double* ec, int ldc, double* u,
 int launch_lex_sweep(sg_ctx* c, int l, double* u, int ldu, const double* f, int ldf, int width, int reverse) {
     const Level& lv = c->levels[l];
     if (lv.nx <= kLexWaveMaxNx)
-        hipLaunchKernelGGL(k_lex_wave<double>, dim3(width), dim3(64), (size_t)2 * lv.N * sizeof(double), c->stream,
+        hipLaunchKernelGGL(k_lex_wave<double>, dim3(width), dim3(64), (size_t)(lv.nx + 2) * (lv.nx + 2) * sizeof(double),
+                           c->stream,
                            lv.sten64, lv.rdiag64, u, ldu, f, ldf, lv.nx, reverse, 0);
     else
         hipLaunchKernelGGL(k_gs_lex<double>, dim3(width), dim3(256), 0, c->stream, lv.sten64, lv.rdiag64, u, ldu, f,
