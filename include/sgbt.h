@@ -195,7 +195,7 @@ int sg_precond_sym(sg_ctx* ctx, const void* R, void* Z, int prec);
  * on the assembled A_hat_l in its natural order -- mode by mode, inside a mode
  * node by node, x fastest -- forward before and backward after the coarse
  * correction, the coarsest level solved directly), D by one K_0 V-cycle per mode.
- * R, Z: device doubles, N x P node-major.  Double precision only.  The first
+ * R, Z: device doubles, N x P node-major, not overlapping.  Double precision only.  The first
  * call builds the coupled hierarchy (host Galerkin products, the coarsest A_hat
  * inverted) and allocates its buffers (about 4 N P doubles).  SG_EINVAL when
  * p < 1, the context's colour mode is not SG_COLOUR_LEX, or the coarsest A_hat

@@ -247,6 +247,21 @@ int ensure_split(sg_ctx* c) {
     int rc = split_setup(c->hs, h);
     if (rc) return rc;
     if ((rc = ensure_mg(c, 0))) return rc;
+    // on a failed allocation everything this call allocated is freed again, so a later call
+    // starts from scratch without stranding device memory
+    const size_t first = c->allocations.size();
+    struct Undo {
+        sg_ctx* c;
+        size_t first;
+        bool armed = true;
+        ~Undo() {
+            if (!armed) return;
+            while (c->allocations.size() > first) {
+                void* q = c->allocations.back();
+                dfree(c, q);
+            }
+        }
+    } undo{c, first};
     const int L = (int)c->levels.size(), p = c->hs.p;
     d.Pa = h.Pa;
     d.npart = h.npart;
@@ -266,6 +281,7 @@ int ensure_split(sg_ctx* c) {
     if ((rc = upload(c, &d.pidx, h.pidx)) || (rc = upload(c, &d.pcoef, h.pcoef)) || (rc = upload(c, &d.cinv, h.cinv)) ||
         (rc = dalloc(c, &d.g, N0 * d.gmax)) || (rc = dalloc(c, &d.s1, N0 * d.Pa)) || (rc = dalloc(c, &d.s2, N0 * d.Pa)))
         return rc;
+    undo.armed = false;
     d.ready = 1;
     return SG_OK;
 }
@@ -284,6 +300,7 @@ int split_cycle(sg_ctx* c, int l, const double* f, int ldf, double* u, int ldu) 
     auto sweep = [&](bool reverse) {
         for (int i = 0; i < p; ++i) {
             const int dd = reverse ? p - 1 - i : i, lo = off[dd], w = off[dd + 1] - lo;
+            if (w == 0) continue;  // an empty degree level (m = 0)
             int e = launch_split_couple(c, l, u, ldu, f, ldf, d.g, w, lo, w, 0);
             if (!e) e = launch_lex_sweep(c, l, u + lo, ldu, d.g, w, w, reverse ? 1 : 0);
             if (e) return e;
@@ -308,6 +325,7 @@ int precond_split(sg_ctx* c, const double* R, double* Z, int sym) {
     const int P = c->hs.P, N = c->hs.N, p = c->hs.p, Pa = d.Pa, Pd = P - Pa;
     const auto& off = c->hs.offsets;
     if ((rc = split_cycle(c, 0, R, P, Z, P))) return rc;
+    if (Pd == 0) return SG_OK;  // no modes of degree p (m = 0): B_T is A_hat alone
     // W couples degree p only with degree p-1: the lower coupling plan of the top level
     const Plan& pd = c->plan_down[p];
     if ((rc = launch_apply(c, pd, Z + pd.in_lo, 0, R + Pa, c->ws.fstage, 0, P, Pd, P))) return rc;

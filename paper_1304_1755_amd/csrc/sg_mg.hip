@@ -1593,6 +1593,8 @@ struct PadLevels {
     int uoff[kMaxFusedLevels];      // LDS element offset of the padded u_l
     int foff[kMaxFusedLevels];      // LDS element offset of f_l (nx^2 values)
     const T* cst[kMaxFusedLevels];  // colour-ordered stencils of the levels above the coarsest
+    const T* sten[kMaxFusedLevels];   // node-ordered stencils and reciprocal diagonals (lexicographic sweeps)
+    const T* rdiag[kMaxFusedLevels];
     int roff;                       // LDS element offset of the residual of the top level
     int p1;                         // transfer of the P1 triangulation (else bilinear)
 };
@@ -1679,6 +1681,53 @@ __device__ __forceinline__ void pad_smooth(const OwnPad<T>& on, T* u, const T* f
         }
 }
 
+// nu lexicographic sweeps (backward when reverse) on the padded grid by the
+// calling wavefront (the first of the workgroup; the caller meets the others
+// at a barrier afterwards): the fronts of k_lex_wave with the neighbour
+// offsets compile-time immediates, the stencils and reciprocal diagonals
+// loaded from global memory and f from LDS kLexAhead fronts ahead
+template <typename T, int NX>
+__device__ __forceinline__ void pad_lex(const T* __restrict__ sten, const T* __restrict__ rdiag, T* u, const T* f,
+                                        bool reverse, int nu) {
+    constexpr int PW = NX + 2;
+    constexpr int ND = 3 * (NX - 1) + 1;
+    const int y = threadIdx.x & 63;
+    for (int sweep = 0; sweep < nu; ++sweep) {
+        auto x_at = [&](int di) -> int { return (reverse ? ND - 1 - di : di) - 2 * y; };
+        auto live = [&](int di, int x) { return di < ND && y < NX && x >= 0 && x < NX; };
+        T st[kLexAhead][9], rd[kLexAhead], rf[kLexAhead];
+        auto fetch = [&](int j, int di) {
+            const int x = x_at(di);
+            const int node = live(di, x) ? y * NX + x : 0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) st[j][t] = sten[(size_t)node * 9 + t];
+            rd[j] = rdiag[node];
+            rf[j] = f[node];
+        };
+#pragma unroll
+        for (int j = 0; j < kLexAhead; ++j) fetch(j, j);
+        for (int di0 = 0; di0 < ND; di0 += kLexAhead) {
+#pragma unroll
+            for (int j = 0; j < kLexAhead; ++j) {
+                const int x = x_at(di0 + j);
+                if (live(di0 + j, x)) {
+                    T* b = u + y * PW + x;  // the south-west neighbour of (x, y)
+                    T lo = rf[j] - st[j][0] * b[0], hi = st[j][6] * b[2 * PW];
+                    lo -= st[j][1] * b[1];
+                    hi += st[j][7] * b[2 * PW + 1];
+                    lo -= st[j][2] * b[2];
+                    hi += st[j][8] * b[2 * PW + 2];
+                    lo -= st[j][3] * b[PW];
+                    hi += st[j][5] * b[PW + 2];
+                    b[PW + 1] = (lo - hi) * rd[j];
+                }
+                fetch(j, di0 + j + kLexAhead);
+                wave_sync();
+            }
+        }
+    }
+}
+
 // calls f(integral_constant<int, nx>) for the level sizes of the padded cycle
 template <typename F>
 __device__ __forceinline__ void with_pad_nx(int nx, F&& f) {
@@ -1694,7 +1743,7 @@ __device__ __forceinline__ void with_pad_nx(int nx, F&& f) {
 
 __host__ __device__ constexpr bool pad_cycle_size(int nx) { return nx == 63 || nx == 31 || nx == 15 || nx == 7 || nx == 3; }
 
-template <typename T>
+template <typename T, bool LEX>
 __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_pad(PadLevels<T> pl, const double* __restrict__ kinv,
                                                                     const T* __restrict__ fin, int ldf,
                                                                     T* __restrict__ uout, int ldu, int nu1, int nu2) {
@@ -1729,7 +1778,12 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_pad(PadLevels<T>
             T* u = lds + pl.uoff[l];
             const T* f = lds + pl.foff[l];
             pad_load_own<T, NX>(pl.cst[l], on, tid);
-            pad_smooth<T, NX>(on, u, f, false, nu1, tid);
+            if constexpr (LEX) {
+                if (threadIdx.x < 64) pad_lex<T, NX>(pl.sten[l], pl.rdiag[l], u, f, false, nu1);
+                __syncthreads();
+            } else {
+                pad_smooth<T, NX>(on, u, f, false, nu1, tid);
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 int x, y;
@@ -1787,7 +1841,12 @@ __global__ void __launch_bounds__(fused4_threads<T>()) k_vcycle_pad(PadLevels<T>
                         [&](int X, int Y) { return ec[(Y + 1) * (NXC + 2) + X + 1]; }, NXC, x, y, pl.p1 != 0);
             }
             __syncthreads();
-            pad_smooth<T, NX>(on, u, f, true, nu2, tid);
+            if constexpr (LEX) {
+                if (threadIdx.x < 64) pad_lex<T, NX>(pl.sten[l], pl.rdiag[l], u, f, true, nu2);
+                __syncthreads();
+            } else {
+                pad_smooth<T, NX>(on, u, f, true, nu2, tid);
+            }
         });
     }
     {
@@ -2015,7 +2074,8 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
     auto uld = [&](int l) { return l == 0 ? ldc0 : width; };
     // the coarse part: the fused LDS cycle from level Lc, or the coarsest solve at level L
     auto coarse_part = [&]() -> int {
-        bool pad = Lc >= 0 && c->opt.colour_mode == SG_COLOUR_FOUR && L - Lc + 1 <= kMaxFusedLevels;
+        const bool lex = c->opt.colour_mode == SG_COLOUR_LEX;
+        bool pad = Lc >= 0 && (c->opt.colour_mode == SG_COLOUR_FOUR || lex) && L - Lc + 1 <= kMaxFusedLevels;
         for (int l = Lc; pad && l < L; ++l)
             pad = pad_cycle_size(c->levels[l].nx) && LevelPtr<T>::cst(c->levels[l]) != nullptr;
         if (pad) {
@@ -2031,11 +2091,19 @@ int vcycle_t(sg_ctx* c, const T* f0, int ldf0, T* u0, int ldu0, int width) {
                 pl.foff[i] = off;
                 off += lv.N;
                 pl.cst[i] = LevelPtr<T>::cst(lv);
+                pl.sten[i] = LevelPtr<T>::s(lv);
+                pl.rdiag[i] = LevelPtr<T>::rd(lv);
             }
             pl.roff = off;
             off += c->levels[Lc].N;
-            hipLaunchKernelGGL(k_vcycle_pad<T>, dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T), c->stream,
-                               pl, (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc), c->opt.nu1, c->opt.nu2);
+            if (lex)
+                hipLaunchKernelGGL((k_vcycle_pad<T, true>), dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T),
+                                   c->stream, pl, (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc),
+                                   c->opt.nu1, c->opt.nu2);
+            else
+                hipLaunchKernelGGL((k_vcycle_pad<T, false>), dim3(width), dim3(fused4_threads<T>()), (size_t)off * sizeof(T),
+                                   c->stream, pl, (const double*)c->kinv, fptr(Lc), fld(Lc), uptr(Lc), uld(Lc),
+                                   c->opt.nu1, c->opt.nu2);
         } else if (Lc >= 0) {
             FusedLevels<T> fl{};
             fl.nlev = L - Lc + 1;

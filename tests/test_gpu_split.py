@@ -56,6 +56,22 @@ def test_split_preconditioner_matches_oracle(disc, n, m, p, sigma, coarsest, sym
     g.close()
 
 
+def test_split_without_random_terms():
+    # m = 0: one mode, so A_hat is K_0 (degree 0) and there is no degree-p block; the split's B_T
+    # is one lexicographic V-cycle of K_0, the level-wise B_T with the same smoother
+    note("split precond m=0")
+    import paper_1304_1755_amd as sgbt
+    g = sgbt.Problem(32, 0, 2, 0.0, corr_len=1.0, coarsest=4, disc="p1", colour="lex")
+    assert g.P == 1
+    R = to_dev(sg_inputs.uniform_block(g.N, g.P, seed=64))
+    Zs = to_host(g.precond(R, kind="tri2x2"))
+    Zt = to_host(g.precond(R, kind="tri"))
+    assert rel_max(Zs, Zt) < 1e-12
+    Zb = to_host(g.precond(R, kind="sym2x2"))
+    assert rel_max(Zb, Zt) < 1e-12
+    g.close()
+
+
 def test_split_with_one_degree_below_the_top_is_the_level_sweep():
     # p = 1: A_hat is the mean block alone, so its coupled cycle is the K_0 V-cycle and the 2x2
     # B_T is the level-wise B_T with the same (lexicographic) smoother
