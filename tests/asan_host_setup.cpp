@@ -1,6 +1,6 @@
 // Host-only driver of the library's setup arithmetic (KL eigenpairs, chaos
 // tables, cell coefficients, multigrid hierarchy, coarsest inverse, coupling
-// plans), built with AddressSanitizer and UndefinedBehaviorSanitizer by
+// plans, the coupled hierarchy of the 2x2 split), built with AddressSanitizer and UndefinedBehaviorSanitizer by
 // tests/test_host_sanitizers.py.  It runs the host code over a spread of
 // options, both discretisations, and checks a few invariants; any memory or
 // undefined-behaviour error aborts the run.
@@ -71,6 +71,62 @@ int main() {
             for (double v : st) checksum += v;
         for (double v : hs.coarse_inv) checksum += v;
         if (!std::isfinite(checksum)) ++bad;
+        // the 2x2 split (Sec. 4.2): K_k on every level, partner tables, the coarsest A_hat inverted
+        const int nxc = hs.mg_n.back() - 1, Nc = nxc * nxc;
+        if (hs.p >= 1 && Nc * hs.offsets[hs.p] <= sg::kSplitMaxCoarse) {
+            sg::SplitHost sp;
+            if (sg::split_setup(hs, sp) != SG_OK) {
+                std::printf("split_setup failed for n=%d m=%d p=%d\n", cs.n, cs.m, cs.p);
+                ++bad;
+            } else {
+                const int Pa = sp.Pa, np = sp.npart;
+                // block k = 0 of every level is the K_0 hierarchy itself
+                for (size_t l = 0; l < hs.mg_sten.size(); ++l)
+                    for (size_t i = 0; i < hs.mg_sten[l].size(); ++i)
+                        if (sp.sten[l][i] != hs.mg_sten[l][i]) { ++bad; break; }
+                // G_k is symmetric: beta lists alpha with the same k and coefficient
+                for (int a = 0; a < Pa; ++a)
+                    for (int q = 0; q < np; ++q) {
+                        const int e = sp.pidx[(size_t)a * np + q];
+                        if (e < 0) continue;
+                        const int b = e & 0xFFFF, k = e >> 16;
+                        bool found = false;
+                        for (int r = 0; r < np; ++r)
+                            if (sp.pidx[(size_t)b * np + r] == (a | (k << 16)) &&
+                                sp.pcoef[(size_t)b * np + r] == sp.pcoef[(size_t)a * np + q])
+                                found = true;
+                        if (!found || b >= Pa || k < 1 || k > hs.m) ++bad;
+                    }
+                // the stored inverse times the coarsest A_hat (assembled again from the tables) is I
+                const int nA = Nc * Pa;
+                const std::vector<double>& sc = sp.sten.back();
+                double worst = 0.0;
+                for (int row = 0; row < nA; ++row) {
+                    const int i = row / Pa, a = row % Pa, y = i / nxc, x = i % nxc;
+                    for (int col = 0; col < nA; ++col) {
+                        double acc = 0.0;
+                        for (int t = 0; t < 9; ++t) {  // (A inv)(row, col) = sum_j A(row, j) inv(j, col)
+                            const int X = x + t % 3 - 1, Y = y + t / 3 - 1;
+                            if (X < 0 || Y < 0 || X >= nxc || Y >= nxc) continue;
+                            const int jn = Y * nxc + X;
+                            acc += sc[(size_t)i * 9 + t] * sp.cinv[((size_t)jn * Pa + a) * nA + col];
+                            for (int q = 0; q < np; ++q) {
+                                const int e = sp.pidx[(size_t)a * np + q];
+                                if (e < 0) continue;
+                                acc += sp.pcoef[(size_t)a * np + q] * sc[((size_t)(e >> 16) * Nc + i) * 9 + t] *
+                                       sp.cinv[((size_t)jn * Pa + (e & 0xFFFF)) * nA + col];
+                            }
+                        }
+                        worst = std::fmax(worst, std::fabs(acc - (row == col ? 1.0 : 0.0)));
+                    }
+                }
+                std::printf("  split: Pa=%d coarsest A_hat %d unknowns, inverse residual %.2e\n", Pa, nA, worst);
+                if (!(worst < 1e-9)) {
+                    std::printf("coarsest A_hat inverse off by %.3e\n", worst);
+                    ++bad;
+                }
+            }
+        }
         std::printf("n=%d m=%d p=%d disc=%d P=%d levels=%zu plans=%zu ok\n", cs.n, cs.m, cs.p, cs.disc, hs.P,
                     hs.mg_n.size(), plans.size());
     }

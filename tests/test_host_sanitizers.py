@@ -3,7 +3,9 @@
 Builds tests/asan_host_setup.cpp together with the library's host setup source
 (host code only, sanitizers on the host pass) and runs it: KL eigenpairs,
 chaos tables, cell coefficients, multigrid hierarchies, coarsest inverses and
-every coupling plan for a spread of options and both discretisations.
+every coupling plan, and the 2x2 split's coupled hierarchy (K_k on every level, symmetric partner
+tables, the coarsest A_hat inverse checked against the assembled matrix) for a spread of options and
+both discretisations.
 """
 
 import os
