@@ -420,8 +420,9 @@ def second_workload(sgbt, stream, name, burst, solves, progress):
     nbytes = apply_bytes(N, P, c["n"], c["m"])
     # steady state, as for the headline workload (whose timed bursts follow a warm-up step): the
     # launch time falls over the first ~30 launches after the host setup leaves the GPU idle
-    # (about 1.1 -> 0.95 ms here), so three warm-up bursts, then three timed ones (HIP events)
-    for _ in range(3 * burst):
+    # (about 1.1 -> 0.95 ms here), so about 0.1 s of warm-up launches, then three timed bursts
+    # (HIP events)
+    for _ in range(8 * burst):
         prob.apply(U, Y)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(burst)]
     ms = []

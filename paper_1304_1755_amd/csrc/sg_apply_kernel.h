@@ -56,7 +56,12 @@ __device__ __forceinline__ int remap_block_xcd(int b, int nb) {
 }
 
 constexpr int kApplyRows = 2;        // grid rows per workgroup
-constexpr int kMinApplyWaves = 16384;  // below this many wavefronts a launch takes shorter segments (narrow coupling plans, small grids)
+// below this many wavefronts a launch takes shorter segments (narrow coupling plans, small grids):
+// a workgroup of fewer wavefronts keeps fewer loads in flight per column, so launches of at most
+// three wavefronts per workgroup ask for four times as many (c4: 1.5 % faster solves, the full
+// 165-mode apply 2 %; the four-wavefront apply at c3 is fastest with the lower bound)
+constexpr int kMinApplyWaves = 16384;
+constexpr int min_apply_waves(int ns) { return ns >= 4 ? kMinApplyWaves : 4 * kMinApplyWaves; }
 
 template <typename F, int... J>
 __device__ __forceinline__ void unroll_steps(F&& f, std::integer_sequence<int, J...>) {
@@ -291,7 +296,7 @@ hipError_t launch_t(hipStream_t st, const Plan& pl, const void* U, int ldu, cons
     // 32-node segments; on small grids shorter ones, down to 8, so that the launch still has
     // enough wavefronts to cover the chip (each segment's walk is sequential)
     int seg = 32;
-    while (seg > 8 && (long)((nx + RW - 1) / RW) * ((nx + seg - 1) / seg) * NS < kMinApplyWaves) seg >>= 1;
+    while (seg > 8 && (long)((nx + RW - 1) / RW) * ((nx + seg - 1) / seg) * NS < min_apply_waves(NS)) seg >>= 1;
     const int nseg = (nx + seg - 1) / seg;
     const int blocks = (nx + RW - 1) / RW * nseg;
     if (R)
