@@ -35,10 +35,10 @@ def _problems(disc, n, m, p, sigma, coarsest):
 
 
 # P1 with a ragged last wavefront of modes (P = 20, 35), several levels and a 3x3 coarsest grid;
-# Q1 with a 7x7 coarsest grid; one degree level below the top (p = 1: A_hat is the mean block);
-# the paper's grid h = 1/64 with fewer modes
+# Q1 with a 7x7 coarsest grid and on the 65x65 grid (P = 35, five levels); one degree level below
+# the top (p = 1: A_hat is the mean block); the paper's grid h = 1/64 with fewer modes
 CASES = [("p1", 16, 3, 3, 0.3, 4), ("p1", 32, 4, 3, 0.4, 4), ("q1", 16, 3, 2, 0.3, 8), ("p1", 16, 4, 1, 0.2, 4),
-         ("p1", 64, 2, 3, 0.4, 4)]
+         ("p1", 64, 2, 3, 0.4, 4), ("q1", 64, 4, 3, 0.4, 4)]
 
 
 @pytest.mark.parametrize("disc,n,m,p,sigma,coarsest", CASES)
