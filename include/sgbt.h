@@ -102,9 +102,10 @@ typedef struct {
                      blocks; 3: B_T with the 2 x 2 split of Sec. 4.2 (see sg_precond_split);
                      4: its symmetric B_S.  3 and 4 need prec SG_F64 and SG_COLOUR_LEX. */
     int prec;     /* SG_F64: double V-cycles; SG_MIXED: float V-cycles, double Krylov and residuals */
-    int restart;  /* FGMRES restart length, 1..64 */
+    int restart;  /* GMRES restart length (solvers 0 and 4), 1..64 */
     int max_it;   /* maximum total iterations */
-    double rtol;  /* stop when ||F - A U||_2 / ||F||_2 < rtol (true residual, double) */
+    double rtol;  /* stop when ||F - A U||_2 / ||F||_2 < rtol (true residual, double); solver 4
+                     stops on the preconditioned residual (see solver) and reports the true one */
     int use_x0;   /* 0: start from U = 0; 1: U holds the initial guess */
     int timing;   /* 1: time the phases with HIP events (fills t_* below) */
 } sg_solve_opts;
