@@ -110,12 +110,12 @@ def test_split_rejects_unsupported_settings():
     g.close()
 
 
-@pytest.mark.parametrize("kind", ["tri2x2", "tri"])
-def test_left_gmres_matches_oracle(kind):
+@pytest.mark.parametrize("kind,restart", [("tri2x2", 10), ("tri", 10), ("tri2x2", 3)])
+def test_left_gmres_matches_oracle(kind, restart):
     # GMRES(10) from the left, stopping on the preconditioned residual: the GPU's count equals the
     # oracle's within one (classical Gram-Schmidt with delayed reorthogonalisation against
-    # modified Gram-Schmidt), and the solution agrees with a direct solve
-    note(f"left gmres {kind}")
+    # modified Gram-Schmidt), and the solution agrees with a direct solve; GMRES(3) restarts
+    note(f"left gmres {kind} restart {restart}")
     g, o, W, Pa, V, H = _problems("p1", 32, 3, 3, 0.4, 4)
     A = system.assemble_A(o)
     F = o.rhs().ravel()
@@ -123,12 +123,35 @@ def test_left_gmres_matches_oracle(kind):
         M = lambda v: bt_literal.precond_tri_2x2(o, v.reshape(o.P, o.N), W, Pa, V, H.vcycle).ravel()  # noqa: E731
     else:
         M = lambda v: precond.precond_tri(o, v.reshape(o.P, o.N), H.vcycle).ravel()  # noqa: E731
-    _x, oinfo = krylov.gmres_left(lambda v: A @ v, F, M, restart=10, tol=1e-10)
-    U, info = g.solve(solver="gmres_left", precond=kind, restart=10, rtol=1e-10, max_it=300)
+    _x, oinfo = krylov.gmres_left(lambda v: A @ v, F, M, restart=restart, tol=1e-10)
+    U, info = g.solve(solver="gmres_left", precond=kind, restart=restart, rtol=1e-10, max_it=300)
     assert info["status"] == 0
     assert abs(info["iters"] - oinfo["iters"]) <= 1, (info["iters"], oinfo["iters"])
+    if info["iters"] > restart:
+        assert info["restarts"] > 0
     Ustar = system.solve_direct(o, A=A)
     assert rel_max(to_host(U).T, Ustar) < 1e-8
+    g.close()
+
+
+def test_left_gmres_from_an_initial_guess():
+    # use_x0: from the converged solution no step is needed; from a perturbed one the solve
+    # converges to the same solution
+    note("left gmres initial guess")
+    import torch
+    g, o, W, Pa, V, H = _problems("p1", 32, 3, 3, 0.3, 4)
+    U, info = g.solve(solver="gmres_left", precond="tri2x2", restart=10, rtol=1e-10, max_it=300)
+    assert info["status"] == 0
+    U1 = U.clone()
+    _, info1 = g.solve(U=U1, solver="gmres_left", precond="tri2x2", restart=10, rtol=1e-9, max_it=300,
+                       use_x0=True)
+    assert info1["status"] == 0 and info1["iters"] == 0, info1
+    pert = torch.from_numpy(sg_inputs.uniform_block(g.N, g.P, seed=65)).to(U.device) * 1e-3
+    U2 = U + pert
+    _, info2 = g.solve(U=U2, solver="gmres_left", precond="tri2x2", restart=10, rtol=1e-10, max_it=300,
+                       use_x0=True)
+    assert info2["status"] == 0 and info2["iters"] > 0
+    assert rel_max(to_host(U2), to_host(U)) < 1e-8
     g.close()
 
 
